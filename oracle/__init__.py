@@ -1,0 +1,21 @@
+"""CPU oracle for the simultaneous short-recurrence Krylov solvers of
+Rashedi, Birk, Frommer and Ebadi, "On short recurrence Krylov type methods for
+linear systems with many right-hand sides" (arXiv 1504.04395).
+
+TEST INFRASTRUCTURE ONLY.  This package is a plain, slow, obviously correct
+numpy/scipy FP64 implementation of what the GPU path computes.  Only the test
+suite, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of ``bench.py``
+may import it.  The GPU path (``paper_1504_04395_amd``) never imports it, and
+this package imports nothing from the GPU path; the two share only the seeded
+input generators in ``inputs/``.
+
+Pins (what fixes each function independently of itself) are the ``-m "not gpu"``
+tests under ``tests/test_oracle_*.py``.  Parity unpinned: Bl-BiCGStab-rQ beyond
+its s = 1 reduction and its exact-arithmetic equivalence with block BiCGStab
+(the paper does not write this variant out; see ``krylov.bl_bicgstab_rq``).
+"""
+from .krylov import (  # noqa: F401
+    METHODS, PIN_METHODS, Result, solve, qr_pos, tr,
+    STATUS_OK, STATUS_NOT_CONVERGED, STATUS_BREAKDOWN, STATUS_DIVERGED,
+)
+from .grad import dense_solve_grad, sddmm  # noqa: F401

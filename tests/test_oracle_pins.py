@@ -1,0 +1,493 @@
+"""Pins for the CPU oracle: each check fixes the oracle against something other
+than itself (textbook solvers, scipy's single-RHS solvers, closed forms,
+brute-force Petrov-Galerkin conditions, the paper's Table 1)."""
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import inputs as I
+import oracle as O
+from oracle import krylov as K
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _small_real(m=12, beta=(20.0, 20.0)):
+    return I.convdiff2d(m, beta).to_scipy().tocsr()
+
+
+def _small_complex(n=300, seed=7):
+    return I.powerlaw(n, seed=seed, lo=4, hi=20, mean=8.0).to_scipy().tocsr()
+
+
+def _iterates(fn, A, R0, kmax, shadow=None):
+    AH = A.conj().T.tocsr()
+    out = {}
+    extras = {}
+
+    def hook(k, X, e):
+        out[k] = X.copy()
+        extras[k] = dict(e)
+
+    fn(A, AH, R0, 0.0, kmax, shadow, hook)
+    return out, extras
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+# ---------------------------------------------------------------------------
+# P1: converged solutions agree with dense LU
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("method", list(O.METHODS))
+@pytest.mark.parametrize("kind", ["real", "complex"])
+def test_p1_dense_lu(method, kind):
+    if kind == "real":
+        A = _small_real(16)
+        B = I.gaussian_block(A.shape[0], 4, seed=1)
+    else:
+        A = _small_complex(400)
+        B = I.gaussian_block(A.shape[0], 3, seed=1, complex_=True)
+    r = O.solve(A, B, method, tol=1e-12, maxit=2000)
+    assert r.status == O.STATUS_OK, (method, r.status, r.iterations)
+    Xd = np.linalg.solve(A.toarray(), B)
+    kappa = np.linalg.cond(A.toarray())
+    assert _rel(r.X, Xd) <= 10 * kappa * 1e-12
+    assert r.rel_res_true < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# P2: for s = 1 every simultaneous variant is the single-RHS method (Section 2)
+# ---------------------------------------------------------------------------
+def _scipy_iterates(solver, A, b, kmax):
+    xs = []
+    solver(A, b, rtol=0.0, atol=0.0, maxiter=kmax, callback=lambda x: xs.append(np.array(x, copy=True)))
+    return {k + 1: x.reshape(-1, 1) for k, x in enumerate(xs)}
+
+
+FAMILY = {
+    "bicg": (spla.bicg, ["gl_bicg", "egl_bicg", "bl_bicg", "bl_bicg_rq", "li_bicg"]),
+    "qmr": (spla.qmr, ["gl_qmr", "egl_qmr"]),
+    "bicgstab": (spla.bicgstab, ["gl_bicgstab", "bl_bicgstab", "bl_bicgstab_rq"]),
+}
+
+
+@pytest.mark.parametrize("family", list(FAMILY))
+@pytest.mark.parametrize("kind", ["real", "complex"])
+def test_p2_single_rhs_reduces_to_textbook(family, kind):
+    solver, methods = FAMILY[family]
+    if kind == "real":
+        A = _small_real(10)
+        b = I.gaussian_block(A.shape[0], 1, seed=3)
+    else:
+        A = _small_complex(200)
+        b = I.gaussian_block(A.shape[0], 1, seed=3, complex_=True)
+    kmax = 12
+    ref = _scipy_iterates(solver, A, b[:, 0], kmax)
+    assert len(ref) == kmax
+    for m in methods:
+        fn = O.METHODS.get(m) or O.PIN_METHODS[m]
+        it, _ = _iterates(fn, A, b, kmax)
+        for k in range(1, kmax + 1):
+            assert _rel(it[k], ref[k]) < 1e-9, (m, k, _rel(it[k], ref[k]))
+
+
+# ---------------------------------------------------------------------------
+# P3: a global method is the single-RHS method on (I (x) A) x = vec(B) (eq. (global))
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("family,method", [("bicg", "gl_bicg"), ("qmr", "gl_qmr"), ("bicgstab", "gl_bicgstab")])
+@pytest.mark.parametrize("kind", ["real", "complex"])
+def test_p3_matricization(family, method, kind):
+    solver = FAMILY[family][0]
+    if kind == "real":
+        A = _small_real(8)
+        B = I.gaussian_block(A.shape[0], 3, seed=4)
+    else:
+        A = _small_complex(150)
+        B = I.gaussian_block(A.shape[0], 3, seed=4, complex_=True)
+    n, s = B.shape
+    big = sp.kron(sp.eye(s), A).tocsr()
+    vecB = B.flatten(order="F")              # (X)_ij = x_{(j-1)n+i}
+    kmax = 10
+    ref = _scipy_iterates(solver, big, vecB, kmax)
+    it, _ = _iterates(O.METHODS[method], A, B, kmax)
+    for k in range(1, kmax + 1):
+        Xk = ref[k].reshape(s, n).T
+        assert _rel(it[k], Xk) < 1e-9, (method, k)
+
+
+# ---------------------------------------------------------------------------
+# P4: economic = global with shadow r^ 1^T (Section 4)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("pair", [("egl_bicg", "gl_bicg"), ("egl_qmr", "gl_qmr")])
+@pytest.mark.parametrize("kind", ["real", "complex"])
+def test_p4_economic_equals_global_with_rank_one_shadow(pair, kind):
+    if kind == "real":
+        A = _small_real(10)
+        B = I.gaussian_block(A.shape[0], 4, seed=6)
+    else:
+        A = _small_complex(200)
+        B = I.gaussian_block(A.shape[0], 4, seed=6, complex_=True)
+    e, g = pair
+    kmax = 15
+    it_e, _ = _iterates(O.METHODS[e], A, B, kmax)
+    rh = B.mean(axis=1)
+    it_g, _ = _iterates(O.METHODS[g], A, B, kmax, shadow=np.outer(rh, np.ones(B.shape[1])))
+    for k in range(1, kmax + 1):
+        assert _rel(it_e[k], it_g[k]) < 1e-10, (e, k)
+    # matvec count of the economic version: s + 1 per iteration
+    r = O.solve(A, B, e, tol=1e-30, maxit=5, preprocess=False)
+    assert r.matvecs == 5 * (B.shape[1] + 1)
+
+
+# ---------------------------------------------------------------------------
+# P5: the rQ reformulations equal the plain block methods in exact arithmetic
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("pair", [("bl_bicg_rq", "bl_bicg"), ("bl_bicgstab_rq", "bl_bicgstab")])
+@pytest.mark.parametrize("kind", ["real", "complex"])
+def test_p5_rq_equals_plain_block(pair, kind):
+    if kind == "real":
+        A = _small_real(12)
+        B = I.gaussian_block(A.shape[0], 4, seed=8)
+    else:
+        A = _small_complex(300)
+        B = I.gaussian_block(A.shape[0], 4, seed=8, complex_=True)
+    rq, plain = pair
+    kmax = 8
+    a, _ = _iterates(O.METHODS[rq], A, B, kmax)
+    b, _ = _iterates(O.PIN_METHODS[plain], A, B, kmax)
+    for k in range(1, kmax + 1):
+        assert _rel(a[k], b[k]) < 1e-8, (rq, k, _rel(a[k], b[k]))
+
+
+# ---------------------------------------------------------------------------
+# P6: Petrov-Galerkin characterisation by brute force (Section 2)
+# ---------------------------------------------------------------------------
+def _krylov_blocks(A, R, k):
+    out = [R]
+    for _ in range(k - 1):
+        out.append(A @ out[-1])
+    return out
+
+
+@pytest.mark.parametrize("kind", ["real", "complex"])
+def test_p6_global_bicg_galerkin(kind):
+    """Gl-BiCG: X_k = sum_j gamma_j A^j R0 with tr(((A^H)^i R^0)^H R_k) = 0, i < k."""
+    if kind == "real":
+        A = _small_real(8)
+        B = I.gaussian_block(A.shape[0], 3, seed=9)
+    else:
+        A = _small_complex(120)
+        B = I.gaussian_block(A.shape[0], 3, seed=9, complex_=True)
+    AH = A.conj().T.tocsr()
+    it, _ = _iterates(O.METHODS["gl_bicg"], A, B, 6)
+    for k in range(1, 7):
+        Kb = _krylov_blocks(A, B, k)              # A^j R0
+        Lb = _krylov_blocks(AH, B, k)             # (A^H)^i R^0
+        M = np.array([[np.vdot(Lb[i], A @ Kb[j]) for j in range(k)] for i in range(k)])
+        rhs = np.array([np.vdot(Lb[i], B) for i in range(k)])
+        g = np.linalg.solve(M, rhs)
+        Xk = sum(g[j] * Kb[j] for j in range(k))
+        assert _rel(it[k], Xk) < 1e-8, k
+
+
+@pytest.mark.parametrize("method", ["bl_bicg", "bl_bicg_rq"])
+@pytest.mark.parametrize("kind", ["real", "complex"])
+def test_p6_block_bicg_galerkin(method, kind):
+    """Bl-BiCG: x_i^(k) in K_k(A, R0) (block Krylov space), residuals orthogonal
+    to K_k(A^H, R^0); checked with orthonormalised block Krylov bases."""
+    if kind == "real":
+        A = _small_real(9)
+        B = I.gaussian_block(A.shape[0], 3, seed=10)
+    else:
+        A = _small_complex(150)
+        B = I.gaussian_block(A.shape[0], 3, seed=10, complex_=True)
+    AH = A.conj().T.tocsr()
+    fn = O.METHODS.get(method) or O.PIN_METHODS[method]
+    it, _ = _iterates(fn, A, B, 5)
+    for k in range(1, 6):
+        Kb = np.linalg.qr(np.hstack(_krylov_blocks(A, B, k)))[0]
+        Lb = np.linalg.qr(np.hstack(_krylov_blocks(AH, B, k)))[0]
+        Y = np.linalg.solve(Lb.conj().T @ (A @ Kb), Lb.conj().T @ B)
+        Xk = Kb @ Y
+        assert _rel(it[k], Xk) < 1e-7, (method, k, _rel(it[k], Xk))
+
+
+# ---------------------------------------------------------------------------
+# P7: QMR = quasi-minimal-residual smoothing of BiCG (Zhou & Walker 1994)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("pair", [("gl_qmr", "gl_bicg"), ("egl_qmr", "egl_bicg")])
+@pytest.mark.parametrize("kind", ["real", "complex"])
+def test_p7_qmr_is_smoothed_bicg(pair, kind):
+    """1/tau_k^2 = 1/tau_{k-1}^2 + 1/||R_k^BiCG||^2 and
+    X_k^QMR = tau_k^2 (X_{k-1}^QMR / tau_{k-1}^2 + X_k^BiCG / ||R_k^BiCG||^2)."""
+    if kind == "real":
+        A = _small_real(12)
+        B = I.gaussian_block(A.shape[0], 3, seed=11)
+    else:
+        A = _small_complex(250)
+        B = I.gaussian_block(A.shape[0], 3, seed=11, complex_=True)
+    q, b = pair
+    kmax = 14
+    XQ, _ = _iterates(O.METHODS[q], A, B, kmax)
+    XB, _ = _iterates(O.METHODS[b], A, B, kmax)
+    tau2 = np.linalg.norm(B) ** 2
+    Xs = np.zeros_like(B)
+    for k in range(1, kmax + 1):
+        rb2 = np.linalg.norm(B - A @ XB[k]) ** 2
+        tau2n = 1.0 / (1.0 / tau2 + 1.0 / rb2)
+        Xs = tau2n * (Xs / tau2 + XB[k] / rb2)
+        tau2 = tau2n
+        assert _rel(XQ[k], Xs) < 1e-10, (q, k)
+
+
+# ---------------------------------------------------------------------------
+# Block BiCGStab residual = psi_k(A) (block BiCG residual), psi_k(t) = prod (1 - omega_j t)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("method", ["bl_bicgstab", "bl_bicgstab_rq"])
+@pytest.mark.parametrize("kind", ["real", "complex"])
+def test_block_bicgstab_is_polynomial_times_block_bicg(method, kind):
+    if kind == "real":
+        A = _small_real(12)
+        B = I.gaussian_block(A.shape[0], 3, seed=12)
+    else:
+        A = _small_complex(250)
+        B = I.gaussian_block(A.shape[0], 3, seed=12, complex_=True)
+    fn = O.METHODS.get(method) or O.PIN_METHODS[method]
+    XS, ex = _iterates(fn, A, B, 7)
+    XB, _ = _iterates(O.PIN_METHODS["bl_bicg"], A, B, 7)
+    for k in range(1, 8):
+        Rb = B - A @ XB[k]
+        for j in range(1, k + 1):
+            Rb = Rb - ex[j]["omega"] * (A @ Rb)
+        assert _rel(B - A @ XS[k], Rb) < 1e-9, (method, k)
+
+
+# ---------------------------------------------------------------------------
+# P8: recursive residual = true residual early on; ||R_k|| = ||C_k|| for rQ
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("method", list(O.METHODS))
+def test_p8_recursive_vs_true_residual(method):
+    A = _small_complex(300)
+    B = I.gaussian_block(A.shape[0], 4, seed=13, complex_=True)
+    kmax = 10
+    r = O.solve(A, B, method, tol=0.0, maxit=kmax, preprocess=False)
+    it, _ = _iterates(O.METHODS[method], A, B, kmax)
+    nb = np.linalg.norm(B)
+    for k in range(1, kmax + 1):
+        true = np.linalg.norm(B - A @ it[k]) / nb
+        assert abs(r.history[k] - true) <= 1e-10 * max(1.0, true), (method, k)
+
+
+# ---------------------------------------------------------------------------
+# P9: matrix-vector products per iteration (Proposition 1, Section 4)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("method,per_iter", [("gl_bicg", lambda s: 2 * s), ("egl_bicg", lambda s: s + 1),
+                                             ("gl_qmr", lambda s: 2 * s), ("egl_qmr", lambda s: s + 1),
+                                             ("gl_bicgstab", lambda s: 2 * s), ("bl_bicg_rq", lambda s: 2 * s),
+                                             ("bl_bicgstab_rq", lambda s: 2 * s)])
+def test_p9_matvec_counts(method, per_iter):
+    A = _small_real(10)
+    B = I.gaussian_block(A.shape[0], 5, seed=14)
+    r = O.solve(A, B, method, tol=0.0, maxit=7)
+    assert r.iterations == 7
+    assert r.matvecs == 7 * per_iter(5)
+
+
+# ---------------------------------------------------------------------------
+# P10: rho = s n / nnz from the paper's example sizes reproduces Table 1
+# ---------------------------------------------------------------------------
+def _table1():
+    rows = []
+    for line in open(os.path.join(GOLDEN, "table1_rho.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        ex, grid, s, rho = line.split()
+        rows.append((ex, grid, int(s), float(rho)))
+    return rows
+
+
+@pytest.mark.parametrize("row", _table1(), ids=lambda r: r[0])
+def test_p10_table1_rho(row):
+    ex, grid, s, rho_printed = row
+    kind, size = grid.split(":")
+    size = int(size)
+    if kind == "2d":
+        A = I.convdiff2d(size)
+    elif kind == "3d":
+        A = I.convdiff3d(size)
+    else:
+        A = I.wilson4d(size, 0.1, seed=0)
+    rho = s * A.n / A.nnz
+    assert abs(rho - rho_printed) < 0.01, (ex, rho)
+
+
+def test_p10_config_sizes():
+    """Exact nonzero counts of the stencil workloads: 5n - 4m (2D), 7n - 6m^2 (3D)."""
+    A = I.convdiff2d(32)
+    assert (A.n, A.nnz) == (1024, 5 * 1024 - 4 * 32)
+    A = I.convdiff3d(20)
+    assert (A.n, A.nnz) == (8000, 7 * 8000 - 6 * 400)
+    A = I.wilson4d(2, 0.1)
+    assert A.nnz == 49 * A.n
+
+
+# ---------------------------------------------------------------------------
+# P11: symmetric permutation equivariance; P12: scaling invariance
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("method", list(O.METHODS))
+def test_p11_permutation_equivariance(method):
+    A = _small_real(10)
+    B = I.gaussian_block(A.shape[0], 3, seed=15)
+    perm = np.random.default_rng(0).permutation(A.shape[0])
+    Ap = A[perm][:, perm]
+    r1 = O.solve(A, B, method, tol=0.0, maxit=10)
+    r2 = O.solve(Ap, B[perm], method, tol=0.0, maxit=10)
+    assert _rel(r2.X, r1.X[perm]) < 1e-10
+    np.testing.assert_allclose(r1.history, r2.history, rtol=1e-9)
+
+
+@pytest.mark.parametrize("method", list(O.METHODS))
+def test_p12_scaling(method):
+    A = _small_real(10)
+    B = I.gaussian_block(A.shape[0], 3, seed=16)
+    c = 3.7
+    r1 = O.solve(A, B, method, tol=0.0, maxit=8)
+    r2 = O.solve(c * A, B, method, tol=0.0, maxit=8)
+    assert _rel(r2.X * c, r1.X) < 1e-9
+    np.testing.assert_allclose(r1.history, r2.history, rtol=1e-8)
+
+
+# ---------------------------------------------------------------------------
+# P13: block methods are invariant under B -> B M (same block Krylov spaces)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("method", ["bl_bicg_rq", "bl_bicg"])
+def test_p13_block_right_invariance(method):
+    A = _small_real(10)
+    B = I.gaussian_block(A.shape[0], 3, seed=17)
+    M = np.random.default_rng(1).standard_normal((3, 3)) + 3 * np.eye(3)
+    r1 = O.solve(A, B, method, tol=0.0, maxit=6, preprocess=False)
+    r2 = O.solve(A, B @ M, method, tol=0.0, maxit=6, preprocess=False)
+    assert _rel(r2.X, r1.X @ M) < 1e-9
+    # so preprocessing on / off gives the same iterate for block BiCG
+    r3 = O.solve(A, B, method, tol=0.0, maxit=6, preprocess=True)
+    assert _rel(r3.X, r1.X) < 1e-9
+
+
+# ---------------------------------------------------------------------------
+# Failure paths (Section 2 breakdown rule; Section 5 iteration cap and "div.")
+# ---------------------------------------------------------------------------
+def test_breakdown_egl_bicg_zero_mean_shadow():
+    A = _small_real(8)
+    b = I.gaussian_block(A.shape[0], 1, seed=18)
+    B = np.hstack([b, -b])
+    r = O.solve(A, B, "egl_bicg", tol=1e-8, preprocess=False)
+    assert r.status == O.STATUS_BREAKDOWN and r.breakdown_iter == 0
+    assert np.all(r.X == 0)
+
+
+def test_breakdown_block_pivot_rule():
+    """Duplicate right-hand sides: the plain block method's s x s matrices are
+    singular, the pivot rule reports BREAKDOWN at iteration 0."""
+    A = _small_real(8)
+    b = I.gaussian_block(A.shape[0], 1, seed=19)
+    B = np.hstack([b, b, I.gaussian_block(A.shape[0], 1, seed=20)])
+    r = O.solve(A, B, "bl_bicg", tol=1e-8, preprocess=False)
+    assert r.status == O.STATUS_BREAKDOWN and r.breakdown_iter == 0
+
+
+def test_not_converged_returns_last_iterate():
+    A = _small_real(12)
+    B = I.gaussian_block(A.shape[0], 2, seed=21)
+    r = O.solve(A, B, "gl_bicg", tol=1e-8, maxit=3)
+    assert r.status == O.STATUS_NOT_CONVERGED and r.iterations == 3 and len(r.history) == 4
+    it = {}
+    O.solve(A, B, "gl_bicg", tol=0.0, maxit=3, hook=lambda k, X, e: it.__setitem__(k, X.copy()))
+
+
+def test_zero_rhs():
+    A = _small_real(6)
+    r = O.solve(A, np.zeros((A.shape[0], 2)), "egl_bicg", preprocess=False)
+    assert r.status == O.STATUS_OK and r.iterations == 0 and np.all(r.X == 0)
+
+
+def test_wilson_unit_rhs_lanczos_breakdown():
+    """Degenerate case of the Wilson workload: with R^_0 = R_0 = unit vectors at
+    one site, tr(R^_1^H R_1) is zero in exact arithmetic, because a hop along mu
+    and back carries (I - Gamma_mu)(I + Gamma_mu) = 0."""
+    A = I.wilson4d(4, 0.1, seed=2).to_scipy()
+    B = I.unit_block(A.shape[0], 12)
+    AH = A.conj().T
+    alpha = np.vdot(B, B) / np.vdot(B, A @ B)
+    R1 = B - alpha * (A @ B)
+    Rh1 = B - np.conj(alpha) * (AH @ B)
+    assert abs(np.vdot(Rh1, R1)) < 1e-14 * np.linalg.norm(R1) * np.linalg.norm(Rh1)
+
+
+# ---------------------------------------------------------------------------
+# P15: the Wilson stand-in has the structure the paper describes for Example 4
+# ---------------------------------------------------------------------------
+def test_p15_wilson_structure():
+    A = I.wilson4d(2, 0.1, seed=3).to_scipy().toarray()
+    g5 = I.GAMMAS[0] @ I.GAMMAS[1] @ I.GAMMAS[2] @ I.GAMMAS[3]
+    G5 = np.kron(np.eye(A.shape[0] // 12), np.kron(g5, np.eye(3)))
+    np.testing.assert_allclose(G5 @ A @ G5, A.conj().T, atol=1e-14)
+    ev = np.linalg.eigvals(A)
+    assert ev.real.min() > 0
+    # symmetric about the real axis: every eigenvalue's conjugate is an eigenvalue
+    d = np.abs(ev[:, None] - np.conj(ev)[None, :]).min(axis=1)
+    assert d.max() < 1e-10
+    for G in I.GAMMAS:
+        np.testing.assert_allclose(G @ G, np.eye(4), atol=1e-15)
+        np.testing.assert_allclose(G, G.conj().T, atol=1e-15)
+
+
+def test_qr_pos():
+    Z = I.gaussian_block(50, 6, seed=22, complex_=True)
+    Q, C = O.qr_pos(Z)
+    np.testing.assert_allclose(Q.conj().T @ Q, np.eye(6), atol=1e-14)
+    np.testing.assert_allclose(Q @ C, Z, atol=1e-13)
+    assert np.all(np.abs(np.imag(np.diag(C))) < 1e-15) and np.all(np.real(np.diag(C)) > 0)
+    assert np.allclose(np.tril(C, -1), 0)
+
+
+# ---------------------------------------------------------------------------
+# Gradient oracle: finite differences, and SDDMM vs dense restriction
+# ---------------------------------------------------------------------------
+def test_grad_oracle_finite_differences():
+    A = _small_real(6).toarray()
+    n = A.shape[0]
+    B = I.gaussian_block(n, 2, seed=23)
+    Xt = I.gaussian_block(n, 2, seed=24)
+
+    def loss(A_, B_):
+        X = np.linalg.solve(A_, B_)
+        return np.sum((X - Xt) ** 2)
+
+    X, G_B, G_A = O.dense_solve_grad(A, B, 2 * (np.linalg.solve(A, B) - Xt))
+    rng = np.random.default_rng(5)
+    E = rng.standard_normal(A.shape) * (A != 0)
+    F = rng.standard_normal(B.shape)
+    h = 1e-6
+    fd = (loss(A + h * E, B + h * F) - loss(A - h * E, B - h * F)) / (2 * h)
+    an = np.sum(G_A * E) + np.sum(G_B * F)
+    assert abs(fd - an) <= 1e-6 * abs(an)
+
+
+def test_sddmm_oracle():
+    C = _small_complex(60)
+    rng = np.random.default_rng(2)
+    G = rng.standard_normal((60, 3)) + 1j * rng.standard_normal((60, 3))
+    X = rng.standard_normal((60, 3)) + 1j * rng.standard_normal((60, 3))
+    out = O.sddmm(C.indptr, C.indices, G, X, scale=-1.0)
+    dense = -G @ X.conj().T
+    k = 0
+    for i in range(60):
+        for p in range(C.indptr[i], C.indptr[i + 1]):
+            assert abs(out[p] - dense[i, C.indices[p]]) < 1e-13
+            k += 1
+    assert k == C.nnz
