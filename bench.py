@@ -1,0 +1,174 @@
+"""Benchmark: solved right-hand sides per second on one MI355X.
+
+Workload: 3D convection-diffusion -Lap u + beta . grad u, 7-point stencil on a
+128^3 grid (n = 2,097,152, nnz = 14,581,760), beta = (30, 20, 10), h = 1/129,
+s = 16 Gaussian right-hand sides, FP64 CSR, relative residual 1e-8.  One step
+solves the 16 right-hand sides once with each of Bl-BiCG-rQ, eGl-QMR and
+Bl-BiCGStab-rQ (48 solved right-hand sides per step).  A, B and X are resident
+in device memory before the timed region.
+
+Also reported: the roofline position of the sparse x block product (the kernel
+every iteration runs; algorithmic bytes A_b + 2 n s 8 per launch, timed with HIP
+events on the stream it runs on) and the CPU oracle's throughput on a bounded
+sample (a few iterations per method, scaled by the GPU's iteration counts).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METHODS = ("bl_bicg_rq", "egl_qmr", "bl_bicgstab_rq")
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def spmm_roofline(pkg, ctx, A, n, nnz, s, stream, reps=50):
+    """Average duration of the CSR sparse x block kernel (same launch
+    configuration as inside the solver) from HIP events on its stream."""
+    import torch
+    X = torch.randn(n, s, dtype=torch.float64, device="cuda")
+    Y = torch.empty_like(X)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        for _ in range(5):
+            pkg.spmm(ctx, A, X, Y)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            pkg.spmm(ctx, A, X, Y)
+        e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    bytes_alg = nnz * (8 + 4) + 4 * (n + 1) + 2 * n * s * 8
+    gbs = bytes_alg / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "k_spmm_csr<double,1,EpiNone>", "avg_us": round(ms * 1e3, 2),
+            "bytes_per_launch": bytes_alg}
+
+
+def cpu_baseline(prob, gpu_iters, iters_per_method=2):
+    """The oracle, untuned, on a bounded sample: `iters_per_method` iterations of
+    each method on the full problem, scaled to a full solve with the GPU's
+    iteration counts."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    s = prob.B.shape[1]
+    total = 0.0
+    for m in METHODS:
+        t = time.perf_counter()
+        oracle.solve(prob.A, prob.B, m, tol=0.0, maxit=iters_per_method)
+        dt = time.perf_counter() - t
+        total += dt / iters_per_method * gpu_iters[m]
+        log(f"cpu oracle {m}: {iters_per_method} iterations in {dt:.1f} s")
+    value = len(METHODS) * s / total
+    return {"value": round(value, 6), "unit": "RHS/s", "cores": cores, "kind": "oracle",
+            "sample": f"{iters_per_method} iterations of each method on the full 128^3 problem, "
+                      f"scaled by the GPU iteration counts {gpu_iters}; numpy/scipy FP64 "
+                      f"(BLAS threads={cores}, scipy sparse products single-threaded)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--grid", type=int, default=128)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is "
+              "described but not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import inputs
+    import paper_1504_04395_amd as pkg
+
+    t0 = time.perf_counter()
+    A_csr = inputs.convdiff3d(args.grid, (30.0, 20.0, 10.0))
+    B_np = inputs.gaussian_block(A_csr.n, 16, seed=0)
+    n, nnz, s = A_csr.n, A_csr.nnz, 16
+    log(f"generated n={n} nnz={nnz} in {time.perf_counter() - t0:.1f} s")
+
+    stream = torch.cuda.Stream()
+    ctx = pkg.Context(0, stream=stream.cuda_stream)
+    A = pkg.Matrix.from_csr(ctx, A_csr)
+    B = torch.from_numpy(B_np).cuda()
+    Xs = {m: torch.zeros_like(B) for m in METHODS}
+    torch.cuda.synchronize()
+
+    infos = {}
+
+    def solve_all(per_method=None):
+        for m in METHODS:
+            tm = time.perf_counter()
+            X, info = pkg.solve(ctx, A, B, m, X=Xs[m], x0_zero=True, tol=args.tol, maxit=20000)
+            if per_method is not None:
+                torch.cuda.synchronize()
+                per_method[m] += time.perf_counter() - tm
+            infos[m] = (X, info)
+
+    for _ in range(args.warmup):
+        solve_all()
+        log("warmup step done: " + ", ".join(f"{m} it={infos[m][1].iterations} st={infos[m][1].status_name}"
+                                             for m in METHODS))
+    torch.cuda.synchronize()
+    times = []
+    per_method = {m: 0.0 for m in METHODS}
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        ts = time.perf_counter()
+        solve_all(per_method)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - ts)
+        log(f"step {k}: {times[-1]:.3f} s")
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    ms_per_step = 1e3 * total / args.steps
+    value = len(METHODS) * s / (total / args.steps)
+
+    roof = spmm_roofline(pkg, ctx, A, n, nnz, s, stream)
+    gpu_iters = {m: infos[m][1].iterations for m in METHODS}
+    out = {
+        "metric": "solved RHS/s at 1e-8 rel. residual (FP64); SpMM HBM GB/s vs peak",
+        "value": round(value, 4), "unit": "RHS/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"convdiff3d-{args.grid}^3-s16", "n": n, "nnz": nnz, "s": s,
+                   "methods": list(METHODS), "tol": args.tol, "format": "csr", "precision": "fp64",
+                   "rhs_per_step": len(METHODS) * s},
+        "per_method": {m: {"iterations": infos[m][1].iterations, "status": infos[m][1].status_name,
+                           "rel_res_true": infos[m][1].rel_res_true,
+                           "s_per_solve": round(per_method[m] / args.steps, 4),
+                           "rhs_per_s": round(s / (per_method[m] / args.steps), 3)} for m in METHODS},
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        prob = inputs.Problem("convdiff3d", A_csr, B_np, METHODS, {})
+        out["cpu_baseline"] = cpu_baseline(prob, gpu_iters, args.cpu_iters)
+    print(json.dumps(out), flush=True)
+    A.close()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,12 @@
+"""MI355X (gfx950) simultaneous short-recurrence Krylov solvers.
+
+Solves A X = B for a sparse non-Hermitian A and a block of s right-hand sides
+with the global, economic-global and QR-stabilised block variants of BiCG, QMR
+and BiCGStab of Rashedi, Birk, Frommer and Ebadi (arXiv 1504.04395).  All
+arithmetic runs in the HIP library ``libskrylov.so`` behind the C ABI of
+``include/skrylov.h``; this package is its ctypes binding.
+"""
+from ._binding import (  # noqa: F401
+    LIB_PATH, METHODS, PRECISIONS, STATUS_NAMES, Context, Matrix, SkrError, SolveInfo, block_qr, load_library,
+    opts_default, sddmm, solve, spmm,
+)

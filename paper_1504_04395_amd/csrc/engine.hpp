@@ -1,0 +1,456 @@
+// Host-side schedules of the simultaneous Krylov methods.
+//
+// One iteration of every method is a fixed sequence of kernel launches on one
+// stream: sparse products (with fused reductions), stage-2 reductions, one
+// one-workgroup coefficient kernel per global reduction, and block updates.
+// The host enqueues `m` iterations at a time (optionally as one captured
+// hipGraph replayed each time) and then reads the 64-byte control block; that
+// read is the only device-to-host transfer inside the iteration.  Kernels
+// return at entry once the control block says the iteration stopped, so the
+// reported iteration count is exact.
+#pragma once
+
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "blk.hpp"
+#include "common.hpp"
+#include "glk.hpp"
+#include "spmm.hpp"
+
+namespace skr {
+
+struct HipError {
+    hipError_t e;
+    const char* what;
+};
+#define SKR_HIP(x)                                   \
+    do {                                             \
+        hipError_t e_ = (x);                         \
+        if (e_ != hipSuccess) throw HipError{e_, #x}; \
+    } while (0)
+#define SKR_LAUNCHED() SKR_HIP(hipGetLastError())
+
+struct Unsupported {
+    std::string what;
+};
+
+// Arena of device memory carved per solve (grow-only, owned by the context).
+struct Arena {
+    char* base = nullptr;
+    size_t cap = 0;
+    size_t off = 0;
+    void* take(size_t bytes) {
+        size_t a = (off + 255) & ~size_t(255);
+        off = a + ((bytes + 255) & ~size_t(255));
+        return base ? base + a : nullptr;
+    }
+};
+
+// A sparse operand (A or A^H) in one storage precision and format.
+template <class T>
+struct Operand {
+    bool sell = false;
+    CsrOp<T> csr{};
+    SellOp<T> sl{};
+};
+
+template <class T>
+struct Env {
+    hipStream_t st{};
+    int n = 0, s = 0;
+    int nb = 0;              // workgroups per streaming kernel (multiple of 8)
+    int rpc = 0;             // rows per workgroup chunk
+    int p2 = 16;             // stage-2 partial count
+    Flat fl{};               // n*s elements
+    Layout ly{};             // row layout of the global family (L = min(2^ceil(log2 s), 16))
+    Layout lyv{};            // vector layout (s = 1, L = 1)
+    Tile16 tl{};             // tile-16 layout of the block family
+    Ctl* ctl = nullptr;
+    double* hist = nullptr;
+    c64* part = nullptr;
+    c64* part2 = nullptr;
+    c64* sc = nullptr;
+    c64* mats = nullptr;
+    Operand<T> A, AH;
+    int J = 1;               // ceil(s/16)
+    size_t blk_bytes() const { return (size_t)n * s * sizeof(T); }
+};
+
+inline int ilog2(int v) {
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+template <class T>
+void env_layout(Env<T>& e, int n, int s) {
+    e.n = n;
+    e.s = s;
+    int L = 1 << ilog2(s);
+    if (L > 16) L = 16;
+    e.ly = Layout{s, L, ilog2(L)};
+    e.lyv = Layout{1, 1, 0};
+    int nb = (n + 63) / 64;
+    nb = ((nb + 7) / 8) * 8;
+    if (nb > 2048) nb = 2048;
+    if (nb < 8) nb = 8;
+    e.nb = nb;
+    e.rpc = (n + nb - 1) / nb;
+    e.rpc = ((e.rpc + 15) / 16) * 16;
+    e.fl.total = (size_t)n * s;
+    size_t per = (e.fl.total + nb - 1) / nb;
+    e.fl.per = ((per + kBlock - 1) / kBlock) * kBlock;
+    e.tl = Tile16{n, s, e.rpc};
+    e.J = (s + 15) / 16;
+}
+
+// ------------------------------------------------------------------ launch helpers
+template <class T, int J, class Epi>
+void spmm_j(Env<T>& e, const Operand<T>& op, const Layout& ly, const T* X, T* Y, Epi epi, const Ctl* ctl) {
+    if (op.sell) {
+        int nchunks = (e.n + op.sl.C - 1) / op.sl.C;
+        int cpb = (nchunks + e.nb - 1) / e.nb;
+        k_spmm_sell<T, J, Epi><<<e.nb, kBlock, 0, e.st>>>(ctl, op.sl, ly, cpb, X, Y, epi);
+    } else {
+        k_spmm_csr<T, J, Epi><<<e.nb, kBlock, 0, e.st>>>(ctl, op.csr, ly, e.rpc, X, Y, epi);
+    }
+    SKR_LAUNCHED();
+}
+template <class T, class Epi>
+void spmm(Env<T>& e, const Operand<T>& op, const Layout& ly, const T* X, T* Y, Epi epi, const Ctl* ctl) {
+    int J = (ly.s + ly.L - 1) / ly.L;
+    if (J == 1) spmm_j<T, 1>(e, op, ly, X, Y, epi, ctl);
+    else spmm_j<T, 2>(e, op, ly, X, Y, epi, ctl);
+}
+template <class T>
+Layout tile_layout(const Env<T>& e) { return Layout{e.s, 16, 4}; }
+
+template <class T>
+void reduce2(Env<T>& e, int E, int cond_slot = -1) {
+    dim3 g((E + kBlock - 1) / kBlock, e.p2);
+    k_reduce_parts<<<g, kBlock, 0, e.st>>>(e.ctl, cond_slot, e.part, e.nb, E, e.part2);
+    SKR_LAUNCHED();
+}
+
+inline size_t mat_lds(int s, int nmat, int ntile) {
+    size_t J = (s + 15) / 16;
+    size_t need = (size_t)nmat * s * s + (size_t)ntile * 16 * s;
+    size_t gram = (16 * J) * (16 * J);
+    return (need > gram ? need : gram) * sizeof(c64);
+}
+
+// CholeskyQR2 (+ shifted first pass) of Z into Q; the Gram Z^H Z partials must
+// already be in e.part.  Final factor in mats (slot 0: M_S / M_SINV, slot 1:
+// M_T / M_TINV).  mode/Other: Gram fused into the final pass (TRI_* flags).
+template <class T, int J>
+void cholqr(Env<T>& e, int slot, const T* Z, T* Q, int mode, const T* Other) {
+    const int s = e.s, ss = s * s;
+    const int base = slot == 0 ? M_S1 : M_T1;
+    size_t lds6 = 6 * (size_t)ss * sizeof(c64);
+    size_t ldsT = mat_lds(s, 1, 1);
+    reduce2(e, ss);
+    k_qr_chol<<<1, kBlock, lds6, e.st>>>(e.ctl, slot, 1, e.n, s, e.part2, e.p2, e.mats);
+    SKR_LAUNCHED();
+    k_bl_tri<T, J><<<e.nb, kBlock, ldsT, e.st>>>(e.ctl, -1, e.tl, TRI_G_OUT_OUT, e.mats, base + 1, Z, nullptr,
+                                                 nullptr, e.part);
+    SKR_LAUNCHED();
+    reduce2(e, ss);
+    k_qr_chol<<<1, kBlock, lds6, e.st>>>(e.ctl, slot, 2, e.n, s, e.part2, e.p2, e.mats);
+    SKR_LAUNCHED();
+    // shifted case only: one more pass with Q2 = Z (S2 S1)^{-1}
+    k_bl_tri<T, J><<<e.nb, kBlock, ldsT, e.st>>>(e.ctl, slot, e.tl, TRI_G_OUT_OUT, e.mats, base + 3, Z, nullptr,
+                                                 nullptr, e.part);
+    SKR_LAUNCHED();
+    reduce2(e, ss, slot);
+    k_qr_chol<<<1, kBlock, lds6, e.st>>>(e.ctl, slot, 3, e.n, s, e.part2, e.p2, e.mats);
+    SKR_LAUNCHED();
+    k_bl_tri<T, J><<<e.nb, kBlock, ldsT, e.st>>>(e.ctl, -1, e.tl, mode | TRI_WRITE, e.mats, base + 5, Z, Q, Other,
+                                                 e.part);
+    SKR_LAUNCHED();
+}
+
+// ------------------------------------------------------------------ methods
+// Each method: `init` enqueues the set-up for the system A D = R0 (R0 in `rhs`,
+// result D in `x`), `iter` enqueues one iteration.  Matrix-vector products per
+// iteration are reported by `mv_per_iter`.
+template <class T>
+struct Method {
+    std::function<void()> init;
+    std::function<void()> iter;
+    long long mv_per_iter = 0;
+};
+
+template <class T>
+Method<T> make_gl_bicg(Env<T>& e, Arena& ar, T* rhs, T* x) {
+    Method<T> m;
+    T* R = (T*)ar.take(e.blk_bytes());
+    T* Rh = (T*)ar.take(e.blk_bytes());
+    T* P = (T*)ar.take(e.blk_bytes());
+    T* Ph = (T*)ar.take(e.blk_bytes());
+    T* Q = (T*)ar.take(e.blk_bytes());
+    T* Zh = (T*)ar.take(e.blk_bytes());
+    m.mv_per_iter = 2LL * e.s;
+    m.init = [=, &e]() {
+        k_copy<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, rhs, R, Rh, P);
+        k_copy<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, rhs, Ph, nullptr, nullptr);
+        k_fill0<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, x, nullptr, nullptr, nullptr);
+        k_flat_nrm_dot<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, R, Rh, e.part);
+        k_s_rho0<<<1, kBlock, 0, e.st>>>(e.part, e.nb, 1, 2, e.sc);
+        k_init_ctl2<<<1, kBlock, 0, e.st>>>(e.ctl, e.hist, e.part, e.nb);
+        SKR_LAUNCHED();
+    };
+    m.iter = [=, &e]() {
+        spmm(e, e.A, e.ly, P, Q, EpiTrace<T>{Ph, e.part}, e.ctl);
+        spmm(e, e.AH, e.ly, Ph, Zh, EpiNone{}, e.ctl);
+        k_s_alpha<<<1, kBlock, 0, e.st>>>(e.ctl, e.part, e.nb, e.sc);
+        k_glbicg_upd<T><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.fl, e.sc, x, R, Rh, P, Q, Zh, e.part);
+        k_s_beta<<<1, kBlock, 0, e.st>>>(e.ctl, e.hist, e.part, e.nb, e.sc);
+        k_glbicg_dir<T><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.fl, e.sc, R, Rh, P, Ph);
+        SKR_LAUNCHED();
+    };
+    return m;
+}
+
+template <class T>
+Method<T> make_egl_bicg(Env<T>& e, Arena& ar, T* rhs, T* x) {
+    Method<T> m;
+    T* R = (T*)ar.take(e.blk_bytes());
+    T* P = (T*)ar.take(e.blk_bytes());
+    T* Q = (T*)ar.take(e.blk_bytes());
+    T* rh = (T*)ar.take((size_t)e.n * sizeof(T));
+    T* ph = (T*)ar.take((size_t)e.n * sizeof(T));
+    T* zh = (T*)ar.take((size_t)e.n * sizeof(T));
+    m.mv_per_iter = e.s + 1;
+    m.init = [=, &e]() {
+        k_copy<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, rhs, R, P, nullptr);
+        k_fill0<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, x, nullptr, nullptr, nullptr);
+        k_row_mean<T><<<(e.n + kBlock - 1) / kBlock, kBlock, 0, e.st>>>(e.n, e.s, rhs, rh);
+        Flat fv{(size_t)e.n, (((size_t)e.n + e.nb - 1) / e.nb + kBlock - 1) / kBlock * kBlock};
+        k_copy<T><<<e.nb, kBlock, 0, e.st>>>(fv, rh, ph, nullptr, nullptr);
+        k_egl_init_red2<T><<<e.nb, kBlock, 0, e.st>>>(e.ly, e.n, e.rpc, R, rh, e.part);
+        k_s_rho0<<<1, kBlock, 0, e.st>>>(e.part, e.nb, 1, 2, e.sc);
+        k_init_ctl2<<<1, kBlock, 0, e.st>>>(e.ctl, e.hist, e.part, e.nb);
+        SKR_LAUNCHED();
+    };
+    m.iter = [=, &e]() {
+        spmm(e, e.A, e.ly, P, Q, EpiVecSum<T>{ph, e.part}, e.ctl);
+        spmm(e, e.AH, e.lyv, ph, zh, EpiNone{}, e.ctl);
+        k_s_alpha<<<1, kBlock, 0, e.st>>>(e.ctl, e.part, e.nb, e.sc);
+        k_eglbicg_upd<T><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.ly, e.n, e.rpc, e.sc, x, R, rh, P, Q, zh, e.part);
+        k_s_beta<<<1, kBlock, 0, e.st>>>(e.ctl, e.hist, e.part, e.nb, e.sc);
+        k_eglbicg_dir<T><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.ly, e.n, e.rpc, e.sc, R, rh, P, ph);
+        SKR_LAUNCHED();
+    };
+    return m;
+}
+
+template <class T>
+Method<T> make_gl_qmr(Env<T>& e, Arena& ar, T* rhs, T* x) {
+    Method<T> m;
+    T* R = (T*)ar.take(e.blk_bytes());
+    T* V = (T*)ar.take(e.blk_bytes());
+    T* W = (T*)ar.take(e.blk_bytes());
+    T* P = (T*)ar.take(e.blk_bytes());
+    T* Qd = (T*)ar.take(e.blk_bytes());
+    T* Pt = (T*)ar.take(e.blk_bytes());
+    T* Zh = (T*)ar.take(e.blk_bytes());
+    T* D = (T*)ar.take(e.blk_bytes());
+    T* S = (T*)ar.take(e.blk_bytes());
+    m.mv_per_iter = 2LL * e.s;
+    m.init = [=, &e]() {
+        k_copy<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, rhs, R, V, W);
+        k_fill0<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, x, D, S, P);
+        k_fill0<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, Qd, nullptr, nullptr, nullptr);
+        k_flat_nrm_dot<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, R, nullptr, e.part);
+        k_init_ctl2<<<1, kBlock, 0, e.st>>>(e.ctl, e.hist, e.part, e.nb);
+        k_gl_init_red3<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, V, W, e.part);
+        k_qmr_s0<<<1, kBlock, 0, e.st>>>(e.ctl, e.part, e.nb, e.sc, 1.0);
+        k_glqmr_step<T><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.fl, e.sc, 0, x, R, D, S, P, Pt, V, W, Qd, e.part);
+        SKR_LAUNCHED();
+    };
+    m.iter = [=, &e]() {
+        spmm(e, e.A, e.ly, P, Pt, EpiTrace<T>{Qd, e.part}, e.ctl);
+        spmm(e, e.AH, e.ly, Qd, Zh, EpiNone{}, e.ctl);
+        k_qmr_s1<<<1, kBlock, 0, e.st>>>(e.ctl, e.part, e.nb, e.sc);
+        k_glqmr_lanczos<T><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.fl, e.sc, V, W, Pt, Zh, e.part);
+        k_qmr_s2<<<1, kBlock, 0, e.st>>>(e.ctl, e.part, e.nb, e.sc, 1.0);
+        k_glqmr_step<T><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.fl, e.sc, 1, x, R, D, S, P, Pt, V, W, Qd, e.part);
+        k_qmr_s3<<<1, kBlock, 0, e.st>>>(e.ctl, e.hist, e.part, e.nb, e.sc);
+        SKR_LAUNCHED();
+    };
+    return m;
+}
+
+template <class T>
+Method<T> make_egl_qmr(Env<T>& e, Arena& ar, T* rhs, T* x) {
+    Method<T> m;
+    T* R = (T*)ar.take(e.blk_bytes());
+    T* V = (T*)ar.take(e.blk_bytes());
+    T* P = (T*)ar.take(e.blk_bytes());
+    T* Pt = (T*)ar.take(e.blk_bytes());
+    T* D = (T*)ar.take(e.blk_bytes());
+    T* S = (T*)ar.take(e.blk_bytes());
+    T* w = (T*)ar.take((size_t)e.n * sizeof(T));
+    T* qd = (T*)ar.take((size_t)e.n * sizeof(T));
+    T* zh = (T*)ar.take((size_t)e.n * sizeof(T));
+    m.mv_per_iter = e.s + 1;
+    const double xs = (double)e.s;
+    m.init = [=, &e]() {
+        k_copy<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, rhs, R, V, nullptr);
+        k_fill0<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, x, D, S, P);
+        k_row_mean<T><<<(e.n + kBlock - 1) / kBlock, kBlock, 0, e.st>>>(e.n, e.s, rhs, w);
+        Flat fv{(size_t)e.n, (((size_t)e.n + e.nb - 1) / e.nb + kBlock - 1) / kBlock * kBlock};
+        k_fill0<T><<<e.nb, kBlock, 0, e.st>>>(fv, qd, nullptr, nullptr, nullptr);
+        k_flat_nrm_dot<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, R, nullptr, e.part);
+        k_init_ctl2<<<1, kBlock, 0, e.st>>>(e.ctl, e.hist, e.part, e.nb);
+        k_egl_init_red<T><<<e.nb, kBlock, 0, e.st>>>(e.ly, e.n, e.rpc, V, w, e.part);
+        k_qmr_s0<<<1, kBlock, 0, e.st>>>(e.ctl, e.part, e.nb, e.sc, xs);
+        k_eglqmr_step<T><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.ly, e.n, e.rpc, e.sc, 0, x, R, D, S, P, Pt, V, w, qd,
+                                                     e.part);
+        SKR_LAUNCHED();
+    };
+    m.iter = [=, &e]() {
+        spmm(e, e.A, e.ly, P, Pt, EpiVecSum<T>{qd, e.part}, e.ctl);
+        spmm(e, e.AH, e.lyv, qd, zh, EpiNone{}, e.ctl);
+        k_qmr_s1<<<1, kBlock, 0, e.st>>>(e.ctl, e.part, e.nb, e.sc);
+        k_eglqmr_lanczos<T><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.ly, e.n, e.rpc, e.sc, V, w, Pt, zh, e.part);
+        k_qmr_s2<<<1, kBlock, 0, e.st>>>(e.ctl, e.part, e.nb, e.sc, xs);
+        k_eglqmr_step<T><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.ly, e.n, e.rpc, e.sc, 1, x, R, D, S, P, Pt, V, w, qd,
+                                                     e.part);
+        k_qmr_s3<<<1, kBlock, 0, e.st>>>(e.ctl, e.hist, e.part, e.nb, e.sc);
+        SKR_LAUNCHED();
+    };
+    return m;
+}
+
+template <class T>
+Method<T> make_gl_bicgstab(Env<T>& e, Arena& ar, T* rhs, T* x) {
+    Method<T> m;
+    T* R = (T*)ar.take(e.blk_bytes());
+    T* Rt = (T*)ar.take(e.blk_bytes());
+    T* P = (T*)ar.take(e.blk_bytes());
+    T* V = (T*)ar.take(e.blk_bytes());
+    T* S = (T*)ar.take(e.blk_bytes());
+    T* Tm = (T*)ar.take(e.blk_bytes());
+    m.mv_per_iter = 2LL * e.s;
+    m.init = [=, &e]() {
+        k_copy<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, rhs, R, Rt, P);
+        k_fill0<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, x, nullptr, nullptr, nullptr);
+        k_flat_nrm_dot<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, R, Rt, e.part);
+        k_s_rho0<<<1, kBlock, 0, e.st>>>(e.part, e.nb, 1, 2, e.sc);
+        k_init_ctl2<<<1, kBlock, 0, e.st>>>(e.ctl, e.hist, e.part, e.nb);
+        SKR_LAUNCHED();
+    };
+    m.iter = [=, &e]() {
+        spmm(e, e.A, e.ly, P, V, EpiTrace<T>{Rt, e.part}, e.ctl);
+        k_s_alpha<<<1, kBlock, 0, e.st>>>(e.ctl, e.part, e.nb, e.sc);
+        k_stab_s<T><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.fl, e.sc, R, V, S);
+        spmm(e, e.A, e.ly, S, Tm, EpiTraceOmega<T>{S, e.part}, e.ctl);
+        k_s_omega<<<1, kBlock, 0, e.st>>>(e.ctl, e.part, e.nb, e.sc);
+        k_stab_upd<T><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.fl, e.sc, x, R, Rt, P, S, Tm, e.part);
+        k_s_stab_beta<<<1, kBlock, 0, e.st>>>(e.ctl, e.hist, e.part, e.nb, e.sc);
+        k_stab_dir<T><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.fl, e.sc, R, V, P);
+        SKR_LAUNCHED();
+    };
+    return m;
+}
+
+template <class T, int J>
+Method<T> make_bl_bicg_rq(Env<T>& e, Arena& ar, T* rhs, T* x) {
+    Method<T> m;
+    T* Q = (T*)ar.take(e.blk_bytes());
+    T* Qh = (T*)ar.take(e.blk_bytes());
+    T* V = (T*)ar.take(e.blk_bytes());
+    T* Vh = (T*)ar.take(e.blk_bytes());
+    T* W = (T*)ar.take(e.blk_bytes());
+    T* Wh = (T*)ar.take(e.blk_bytes());
+    T* Z = (T*)ar.take(e.blk_bytes());
+    T* Zh = (T*)ar.take(e.blk_bytes());
+    m.mv_per_iter = 2LL * e.s;
+    const int s = e.s, ss = s * s;
+    const Layout lt = tile_layout(e);
+    m.init = [=, &e]() {
+        k_fill0<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, x, nullptr, nullptr, nullptr);
+        k_bl_gram<T, J><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.tl, rhs, rhs, e.part);
+        SKR_LAUNCHED();
+        cholqr<T, J>(e, 0, rhs, Q, TRI_G_OUT_OUT, nullptr);   // Q0, C0 = S, M = Q0^H Q0
+        reduce2(e, ss);
+        k_bl_init<<<1, kBlock, 6 * (size_t)ss * sizeof(c64), e.st>>>(e.ctl, e.hist, s, 1, e.part2, e.p2, M_M,
+                                                                      e.mats);
+        k_copy<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, Q, Qh, V, Vh);
+        SKR_LAUNCHED();
+    };
+    m.iter = [=, &e]() {
+        spmm_j<T, J>(e, e.A, lt, V, W, EpiGram<T, J>{Vh, e.part}, e.ctl);           // W = A V, G = V^^H W
+        spmm_j<T, J>(e, e.AH, lt, Vh, Wh, EpiNone{}, e.ctl);                      // W^ = A^H V^
+        reduce2(e, ss);
+        k_blrq_alpha<<<1, kBlock, 6 * (size_t)ss * sizeof(c64), e.st>>>(e.ctl, s, e.part2, e.p2, e.mats, e.sc);
+        k_blrq_updz<T, J><<<e.nb, kBlock, mat_lds(s, 2, 2), e.st>>>(e.ctl, e.tl, e.mats, x, V, Q, W, Z, e.part);
+        SKR_LAUNCHED();
+        cholqr<T, J>(e, 0, Z, Q, 0, nullptr);                                     // Q' S = Q - W alpha
+        k_bl_axpm<T, J, true><<<e.nb, kBlock, mat_lds(s, 1, 1), e.st>>>(e.ctl, e.tl, e.mats, M_ALPHAH, e.sc, 0,
+                                                                       Qh, Wh, nullptr, Zh, e.part);
+        SKR_LAUNCHED();
+        cholqr<T, J>(e, 1, Zh, Qh, TRI_G_OUT_OTHER, Q);                           // Q^' S^, M' = Q^'^H Q'
+        reduce2(e, ss);
+        k_blrq_beta<<<1, kBlock, 6 * (size_t)ss * sizeof(c64), e.st>>>(e.ctl, e.hist, s, e.part2, e.p2, e.mats);
+        k_bl_axpm<T, J, false><<<e.nb, kBlock, mat_lds(s, 1, 1), e.st>>>(e.ctl, e.tl, e.mats, M_BETA, e.sc, 0,
+                                                                        Q, V, nullptr, V, e.part);
+        k_bl_axpm<T, J, false><<<e.nb, kBlock, mat_lds(s, 1, 1), e.st>>>(e.ctl, e.tl, e.mats, M_BETAH, e.sc, 0,
+                                                                        Qh, Vh, nullptr, Vh, e.part);
+        SKR_LAUNCHED();
+    };
+    return m;
+}
+
+template <class T, int J>
+Method<T> make_bl_bicgstab_rq(Env<T>& e, Arena& ar, T* rhs, T* x) {
+    Method<T> m;
+    T* Q = (T*)ar.take(e.blk_bytes());
+    T* U = (T*)ar.take(e.blk_bytes());
+    T* W = (T*)ar.take(e.blk_bytes());
+    T* St = (T*)ar.take(e.blk_bytes());
+    T* Tt = (T*)ar.take(e.blk_bytes());
+    T* Z = (T*)ar.take(e.blk_bytes());
+    T* Rt = (T*)ar.take(e.blk_bytes());
+    m.mv_per_iter = 2LL * e.s;
+    const int s = e.s, ss = s * s;
+    const Layout lt = tile_layout(e);
+    m.init = [=, &e]() {
+        k_copy<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, rhs, Rt, nullptr, nullptr);
+        k_fill0<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, x, nullptr, nullptr, nullptr);
+        k_bl_gram<T, J><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.tl, rhs, rhs, e.part);
+        SKR_LAUNCHED();
+        cholqr<T, J>(e, 0, rhs, Q, TRI_G_OTHER_OUT, Rt);                         // Q0, N = R~^H Q0
+        reduce2(e, ss);
+        k_bl_init<<<1, kBlock, 6 * (size_t)ss * sizeof(c64), e.st>>>(e.ctl, e.hist, s, 0, e.part2, e.p2, M_N,
+                                                                      e.mats);
+        k_copy<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, Q, U, nullptr, nullptr);
+        SKR_LAUNCHED();
+    };
+    m.iter = [=, &e]() {
+        spmm_j<T, J>(e, e.A, lt, U, W, EpiGram<T, J>{Rt, e.part}, e.ctl);           // W = A U, G = R~^H W
+        reduce2(e, ss);
+        k_blst_a<<<1, kBlock, 6 * (size_t)ss * sizeof(c64), e.st>>>(e.ctl, s, e.part2, e.p2, e.mats, e.sc);
+        k_bl_axpm<T, J, false><<<e.nb, kBlock, mat_lds(s, 1, 1), e.st>>>(e.ctl, e.tl, e.mats, M_TMP, e.sc, 0,
+                                                                        Q, W, nullptr, St, e.part);  // S~ = Q - W a
+        SKR_LAUNCHED();
+        spmm_j<T, J>(e, e.A, lt, St, Tt, EpiGramOmega<T, J>{St, e.part}, e.ctl);    // T~ = A S~
+        reduce2(e, 2 * ss);
+        k_blst_omega<<<1, kBlock, 6 * (size_t)ss * sizeof(c64), e.st>>>(e.ctl, s, e.part2, e.p2, e.mats, e.sc);
+        k_blst_upd<T, J><<<e.nb, kBlock, mat_lds(s, 2, 2), e.st>>>(e.ctl, e.tl, e.mats, e.sc, x, U, St, Tt, Z,
+                                                                  e.part);
+        SKR_LAUNCHED();
+        cholqr<T, J>(e, 0, Z, Q, TRI_G_OTHER_OUT, Rt);                            // Q' Sigma = Z, N' = R~^H Q'
+        reduce2(e, ss);
+        k_blst_b<<<1, kBlock, 6 * (size_t)ss * sizeof(c64), e.st>>>(e.ctl, e.hist, s, e.part2, e.p2, e.mats, e.sc);
+        k_bl_axpm<T, J, false><<<e.nb, kBlock, mat_lds(s, 1, 1), e.st>>>(e.ctl, e.tl, e.mats, M_B, e.sc,
+                                                                        SC_GAMMA, Q, U, W, U, e.part);
+        SKR_LAUNCHED();
+    };
+    return m;
+}
+
+}  // namespace skr

@@ -1,0 +1,274 @@
+// Sparse matrix x block products Y = A X for row-major n x s blocks.
+//
+// CSR: a group of L lanes owns one row; each lane owns columns lane + L*j
+// (j < J) of the block, so every stored nonzero a_ij is read once for all s
+// right-hand sides and the s values X[j, :] are one contiguous read
+// (Section 1: "reading and storing A only once while updating the iterates for
+// all s r.h.s. simultaneously").
+//
+// SELL-C-sigma: rows are sorted by length inside windows of sigma rows and cut
+// into chunks of C rows; a chunk stores its entries column-major (slot k of all
+// C rows together), padded to the chunk's longest row.  A group of L lanes
+// still owns one row; the padding entries have value 0 and column = row.
+//
+// Epilogues fold the reductions the solvers need right after the product into
+// the same pass (the output row is still in registers): traces tr(Z^H Y),
+// eGl's sum(z^H Y) and s x s Gram matrices (MFMA, tile-16 layout).
+#pragma once
+
+#include "common.hpp"
+
+namespace skr {
+
+template <class T>
+struct CsrOp {
+    int n;
+    const int* __restrict__ rp;
+    const int* __restrict__ ci;
+    const T* __restrict__ va;
+};
+
+template <class T>
+struct SellOp {
+    int n;
+    int C;                          // chunk height (rows)
+    const int* __restrict__ cptr;   // chunk start offsets (nchunks + 1), in entries
+    const int* __restrict__ clen;   // chunk width (slots)
+    const int* __restrict__ row;    // sorted position -> original row
+    const int* __restrict__ ci;     // column of each slot
+    const T* __restrict__ va;       // value of each slot (0 for padding)
+};
+
+struct Layout {
+    int s;      // block width
+    int L;      // lanes per row (power of two, <= 16)
+    int lgL;
+};
+
+// ------------------------------------------------------------------ epilogues
+struct EpiNone {
+    struct St {};
+    __device__ void init(St&) {}
+    template <class T, int J>
+    __device__ void row(St&, int, bool, int, const Layout&, const T (&)[J]) {}
+    __device__ void finish(St&, int) {}
+};
+
+// part[block] = sum_rows sum_c conj(Z[i,c]) * Y[i,c]   (tr(Z^H Y))
+template <class T>
+struct EpiTrace {
+    const T* __restrict__ Z;
+    c64* part;
+    struct St { c64 acc[1]; };
+    __device__ void init(St& st) { st.acc[0] = {0.0, 0.0}; }
+    template <int J>
+    __device__ void row(St& st, int i, bool valid, int lane, const Layout& ly, const T (&y)[J]) {
+        if (!valid) return;
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            int c = lane + ly.L * j;
+            if (c < ly.s) dot_acc(st.acc[0], Z[(size_t)i * ly.s + c], y[j]);
+        }
+    }
+    __device__ void finish(St& st, int b) { block_reduce_store<1>(st.acc, part + (size_t)b); }
+};
+
+// part[block] = sum_i conj(z_i) sum_c Y[i,c]   (sum(z^H Y), economic variants)
+template <class T>
+struct EpiVecSum {
+    const T* __restrict__ z;
+    c64* part;
+    struct St { c64 acc[1]; };
+    __device__ void init(St& st) { st.acc[0] = {0.0, 0.0}; }
+    template <int J>
+    __device__ void row(St& st, int i, bool valid, int lane, const Layout& ly, const T (&y)[J]) {
+        if (!valid) return;
+        T zi = z[i];
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            int c = lane + ly.L * j;
+            if (c < ly.s) dot_acc(st.acc[0], zi, y[j]);
+        }
+    }
+    __device__ void finish(St& st, int b) { block_reduce_store<1>(st.acc, part + (size_t)b); }
+};
+
+// part[block] = (tr(Y^H Z), tr(Y^H Y))  -- BiCGStab's omega step with Y = A S, Z = S
+template <class T>
+struct EpiTraceOmega {
+    const T* __restrict__ Z;
+    c64* part;
+    struct St { c64 acc[2]; };
+    __device__ void init(St& st) { st.acc[0] = {0.0, 0.0}; st.acc[1] = {0.0, 0.0}; }
+    template <int J>
+    __device__ void row(St& st, int i, bool valid, int lane, const Layout& ly, const T (&y)[J]) {
+        if (!valid) return;
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            int c = lane + ly.L * j;
+            if (c < ly.s) {
+                dot_acc(st.acc[0], y[j], Z[(size_t)i * ly.s + c]);
+                dot_acc(st.acc[1], y[j], y[j]);
+            }
+        }
+    }
+    __device__ void finish(St& st, int b) { block_reduce_store<2>(st.acc, part + (size_t)b * 2); }
+};
+
+// part[block] = Z^H Y (s x s), requires L = 16 (tile-16 layout)
+template <class T, int J>
+struct EpiGram {
+    const T* __restrict__ Z;
+    c64* part;
+    struct St { GramAcc<J, Tr<T>::cplx> g; };
+    __device__ void init(St& st) { st.g.clear(); }
+    __device__ void row(St& st, int i, bool valid, int lane, const Layout& ly, const T (&y)[J]) {
+        c64 zv[J], yv[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            int c = lane + 16 * j;
+            bool ok = valid && c < ly.s;
+            zv[j] = ok ? up(Z[(size_t)i * ly.s + c]) : c64{0.0, 0.0};
+            yv[j] = ok ? up(y[j]) : c64{0.0, 0.0};
+        }
+        st.g.add(zv, yv);
+    }
+    __device__ void finish(St& st, int b, int s) {
+        __shared__ c64 lds[(16 * J) * (16 * J)];
+        st.g.store(s, lds, part + (size_t)b * s * s);
+    }
+};
+
+// part[block] = (Y^H Z, Y^H Y) as two s x s matrices -- Bl-BiCGStab-rQ omega step
+template <class T, int J>
+struct EpiGramOmega {
+    const T* __restrict__ Z;
+    c64* part;
+    struct St { GramAcc<J, Tr<T>::cplx> g1, g2; };
+    __device__ void init(St& st) { st.g1.clear(); st.g2.clear(); }
+    __device__ void row(St& st, int i, bool valid, int lane, const Layout& ly, const T (&y)[J]) {
+        c64 zv[J], yv[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            int c = lane + 16 * j;
+            bool ok = valid && c < ly.s;
+            zv[j] = ok ? up(Z[(size_t)i * ly.s + c]) : c64{0.0, 0.0};
+            yv[j] = ok ? up(y[j]) : c64{0.0, 0.0};
+        }
+        st.g1.add(yv, zv);
+        st.g2.add(yv, yv);
+    }
+    __device__ void finish(St& st, int b, int s) {
+        __shared__ c64 lds[(16 * J) * (16 * J)];
+        st.g1.store(s, lds, part + (size_t)b * 2 * s * s);
+        st.g2.store(s, lds, part + (size_t)b * 2 * s * s + s * s);
+    }
+};
+
+template <class E> struct EpiIsGram { static constexpr bool value = false; };
+template <class T, int J> struct EpiIsGram<EpiGram<T, J>> { static constexpr bool value = true; };
+template <class T, int J> struct EpiIsGram<EpiGramOmega<T, J>> { static constexpr bool value = true; };
+
+template <class E, int J>
+__device__ inline void epi_finish(E& e, typename E::St& st, int b, int s) {
+    if constexpr (EpiIsGram<E>::value) e.finish(st, b, s);
+    else e.finish(st, b);
+}
+
+// ------------------------------------------------------------------ kernels
+// Workgroup b (after the XCD remap) owns rows [chunk*rows_per_chunk, ...).
+template <class T, int J, class Epi>
+__global__ __launch_bounds__(kBlock) void k_spmm_csr(const Ctl* ctl, CsrOp<T> A, Layout ly, int rows_per_chunk,
+                                                      const T* __restrict__ X, T* __restrict__ Y, Epi epi) {
+    if (stopped(ctl)) return;
+    const int tid = threadIdx.x;
+    const int lane = tid & (ly.L - 1);
+    const int grp = tid >> ly.lgL;
+    const int rpb = kBlock >> ly.lgL;
+    const int chunk = xcd_chunk(blockIdx.x, gridDim.x);
+    const int r0 = chunk * rows_per_chunk;
+    const int r1 = min(A.n, r0 + rows_per_chunk);
+    const int s = ly.s;
+    typename Epi::St st;
+    epi.init(st);
+    for (int base = r0; base < r1; base += rpb) {
+        const int i = base + grp;
+        const bool valid = i < r1;
+        T acc[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) acc[j] = zero<T>();
+        if (valid) {
+            const int k0 = A.rp[i], k1 = A.rp[i + 1];
+            for (int k = k0; k < k1; ++k) {
+                const int c = A.ci[k];
+                const T a = A.va[k];
+                const T* __restrict__ xr = X + (size_t)c * s;
+#pragma unroll
+                for (int j = 0; j < J; ++j) {
+                    int col = lane + ly.L * j;
+                    if (col < s) acc[j] = fma_(a, xr[col], acc[j]);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                int col = lane + ly.L * j;
+                if (col < s) Y[(size_t)i * s + col] = acc[j];
+            }
+        }
+        epi.row(st, i, valid, lane, ly, acc);
+    }
+    epi_finish<Epi, J>(epi, st, blockIdx.x, s);
+}
+
+template <class T, int J, class Epi>
+__global__ __launch_bounds__(kBlock) void k_spmm_sell(const Ctl* ctl, SellOp<T> A, Layout ly, int chunks_per_block,
+                                                       const T* __restrict__ X, T* __restrict__ Y, Epi epi) {
+    if (stopped(ctl)) return;
+    const int tid = threadIdx.x;
+    const int lane = tid & (ly.L - 1);
+    const int grp = tid >> ly.lgL;
+    const int rpb = kBlock >> ly.lgL;
+    const int s = ly.s;
+    const int nchunks = (A.n + A.C - 1) / A.C;
+    const int cb = xcd_chunk(blockIdx.x, gridDim.x) * chunks_per_block;
+    const int ce = min(nchunks, cb + chunks_per_block);
+    const int pb = cb * A.C;
+    const int pe = min(A.n, ce * A.C);
+    typename Epi::St st;
+    epi.init(st);
+    for (int base = pb; base < pe; base += rpb) {
+        const int p = base + grp;                // sorted position
+        const bool valid = p < pe;
+        T acc[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) acc[j] = zero<T>();
+        int i = 0;
+        if (valid) {
+            const int ch = p / A.C;
+            const int r = p - ch * A.C;
+            i = A.row[p];
+            const int w = A.clen[ch];
+            const int e0 = A.cptr[ch] + r;
+            for (int k = 0; k < w; ++k) {
+                const int e = e0 + k * A.C;
+                const int c = A.ci[e];
+                const T a = A.va[e];
+                const T* __restrict__ xr = X + (size_t)c * s;
+#pragma unroll
+                for (int j = 0; j < J; ++j) {
+                    int col = lane + ly.L * j;
+                    if (col < s) acc[j] = fma_(a, xr[col], acc[j]);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                int col = lane + ly.L * j;
+                if (col < s) Y[(size_t)i * s + col] = acc[j];
+            }
+        }
+        epi.row(st, i, valid, lane, ly, acc);
+    }
+    epi_finish<Epi, J>(epi, st, blockIdx.x, s);
+}
+
+}  // namespace skr

@@ -1,0 +1,299 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs."""
+import os
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import inputs as I
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+METHODS = ["gl_bicg", "egl_bicg", "gl_qmr", "egl_qmr", "gl_bicgstab", "bl_bicg_rq", "bl_bicgstab_rq"]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1504_04395_amd as P
+    P.load_library()
+    return P
+
+
+@pytest.fixture(scope="module")
+def ctx(pkg):
+    c = pkg.Context(0)
+    yield c
+    c.close()
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+# ---------------------------------------------------------------- SpMM
+def _ragged_matrix(n, complex_, seed):
+    """Random sparse matrix with empty rows, a few long rows and a ragged tail."""
+    rng = np.random.default_rng(seed)
+    lens = rng.integers(0, 9, size=n)
+    lens[rng.choice(n, size=max(1, n // 50), replace=False)] = 0
+    lens[rng.choice(n, size=3, replace=False)] = min(n, 300)
+    rows, cols = [], []
+    for i, L in enumerate(lens):
+        c = np.sort(rng.choice(n, size=int(min(L, n)), replace=False))
+        rows.append(np.full(len(c), i)); cols.append(c)
+    rows = np.concatenate(rows); cols = np.concatenate(cols)
+    vals = rng.standard_normal(rows.size)
+    if complex_:
+        vals = vals + 1j * rng.standard_normal(rows.size)
+    M = sp.csr_array((vals, (rows, cols)), shape=(n, n))
+    M.sort_indices()
+    return I.CSR(n, M.indptr.astype(np.int64), M.indices.astype(np.int32), M.data)
+
+
+@pytest.mark.parametrize("fmt", ["csr", "sell"])
+@pytest.mark.parametrize("kind", ["real", "complex"])
+@pytest.mark.parametrize("s", [1, 2, 3, 4, 8, 12, 16, 17, 32])
+def test_spmm_matches_scipy(pkg, ctx, fmt, kind, s):
+    n = 1000 + 37
+    C = _ragged_matrix(n, kind == "complex", seed=s)
+    say("spmm", fmt, kind, s)
+    A = pkg.Matrix.from_csr(ctx, C, fmt=fmt, sell_C=32, sell_sigma=128)
+    X = I.gaussian_block(n, s, seed=s + 1, complex_=(kind == "complex"))
+    Sa = C.to_scipy()
+    for adj in (False, True):
+        Y = pkg.spmm(ctx, A, X, adjoint=adj)
+        ref = (Sa.conj().T @ X) if adj else (Sa @ X)
+        scale = np.abs(Sa).max() * np.abs(X).max() * 300
+        np.testing.assert_allclose(Y, ref, rtol=0, atol=1e-14 * scale)
+    A.close()
+
+
+def test_spmm_device_tensors(pkg, ctx):
+    import torch
+    P = I.config(2, "small")
+    A = pkg.Matrix.from_csr(ctx, P.A)
+    Xd = torch.from_numpy(P.B).cuda()
+    Y = pkg.spmm(ctx, A, Xd)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(Y.cpu().numpy(), P.A.to_scipy() @ P.B, rtol=1e-13, atol=1e-13)
+    A.close()
+
+
+# ---------------------------------------------------------------- QR and SDDMM
+@pytest.mark.parametrize("kind", ["real", "complex"])
+@pytest.mark.parametrize("s", [1, 4, 12, 16, 32])
+def test_block_qr(pkg, ctx, kind, s):
+    Z = I.gaussian_block(5000 + 3, s, seed=s, complex_=(kind == "complex"))
+    Q, Cm, rc = pkg.block_qr(ctx, Z)
+    assert rc == 0
+    np.testing.assert_allclose(Q.conj().T @ Q, np.eye(s), atol=1e-13)
+    np.testing.assert_allclose(Q @ Cm, Z, atol=1e-12 * np.abs(Z).max())
+    Qo, Co = O.qr_pos(Z)            # unique QR with positive diagonal
+    assert _rel(Cm, Co) < 1e-12
+    assert np.allclose(np.tril(Cm, -1), 0)
+
+
+def test_block_qr_ill_conditioned_uses_shift(pkg, ctx):
+    rng = np.random.default_rng(3)
+    U, _ = np.linalg.qr(rng.standard_normal((4000, 8)))
+    Z = U @ np.diag(10.0 ** -np.arange(8) * 1.5) @ np.linalg.qr(rng.standard_normal((8, 8)))[0]
+    Q, Cm, rc = pkg.block_qr(ctx, Z)
+    assert rc == 0
+    # kappa(Z) ~ 1e10: plain CholeskyQR2 would fail; the shifted pass keeps Q
+    # orthonormal to ~1e-10 and the factorisation exact to rounding
+    np.testing.assert_allclose(Q.T @ Q, np.eye(8), atol=1e-10)
+    np.testing.assert_allclose(Q @ Cm, Z, atol=1e-13)
+
+
+@pytest.mark.parametrize("kind", ["real", "complex"])
+@pytest.mark.parametrize("s", [1, 3, 8, 32])
+def test_sddmm(pkg, ctx, kind, s):
+    n = 777
+    C = _ragged_matrix(n, kind == "complex", seed=40 + s)
+    A = pkg.Matrix.from_csr(ctx, C)
+    G = I.gaussian_block(n, s, seed=1, complex_=(kind == "complex"))
+    X = I.gaussian_block(n, s, seed=2, complex_=(kind == "complex"))
+    out = pkg.sddmm(ctx, A, G, X, scale=-1.0)
+    ref = O.sddmm(C.indptr, C.indices, G, X, scale=-1.0)
+    np.testing.assert_allclose(out, ref, rtol=1e-13, atol=1e-13 * np.abs(ref).max())
+    A.close()
+
+
+# ---------------------------------------------------------------- solver parity
+def _problem(k):
+    P = I.config(k, "small")
+    if k == 3:   # unit-vector RHS break the BiCG/QMR families exactly (Lanczos breakdown); use Gaussian RHS
+        B = I.gaussian_block(P.A.n, 12, seed=0, complex_=True)
+        return P.A, B, P.name + "-gaussRHS"
+    return P.A, P.B, P.name
+
+
+CASES = [(k, m) for k in (1, 2, 3, 4, 5) for m in METHODS]
+
+
+def _self_sensitivity(Acsr, B, method, ref, **kw):
+    """The oracle's own spread: the same solve with B perturbed by 1e-15
+    (relative, fixed seed).  Krylov recurrences amplify rounding differences,
+    so two correct FP64 implementations can only agree to about this level."""
+    rng = np.random.default_rng(12345)
+    pert = B * (1 + 1e-15 * (rng.standard_normal(B.shape) if not np.iscomplexobj(B)
+                             else rng.standard_normal(B.shape) + 1j * rng.standard_normal(B.shape)))
+    r2 = O.solve(Acsr, pert, method, **kw)
+    h = min(len(ref.history), len(r2.history))
+    hist = np.abs(ref.history[:h] - r2.history[:h]) / ref.history[:h]
+    return _rel(r2.X, ref.X), hist, abs(r2.iterations - ref.iterations)
+
+
+@pytest.mark.parametrize("k,method", CASES)
+def test_solve_matches_oracle(pkg, ctx, k, method):
+    """Converged parity: same status, iteration count within 5% (plus the
+    oracle's own spread), X within 100x the oracle's own sensitivity to 1e-15
+    input perturbations (floor 1e-10), true residual at the stopping level."""
+    Acsr, B, name = _problem(k)
+    say("solve", name, method)
+    ref = O.solve(Acsr, B, method, tol=1e-8, maxit=3000)
+    xs, hs, its = _self_sensitivity(Acsr, B, method, ref, tol=1e-8, maxit=3000)
+    A = pkg.Matrix.from_csr(ctx, Acsr)
+    X, info = pkg.solve(ctx, A, B, method, tol=1e-8, maxit=3000)
+    A.close()
+    err = _rel(X, ref.X)
+    say(f"  gpu status={info.status_name} it={info.iterations} res={info.rel_res_true:.3e} | "
+        f"oracle status={ref.status} it={ref.iterations} res={ref.rel_res_true:.3e} | "
+        f"err={err:.3e} oracle-self-spread={xs:.3e}")
+    assert info.status == ref.status
+    assert abs(info.iterations - ref.iterations) <= max(1, int(0.05 * ref.iterations)) + its
+    assert info.matvecs * ref.iterations == ref.matvecs * info.iterations
+    # the first iterations agree to rounding (before amplification sets in)
+    m = min(8, len(ref.history), len(info.history))
+    np.testing.assert_allclose(info.history[:m], ref.history[:m], rtol=1e-9, atol=0)
+    # later iterations: within 100x the oracle's own spread
+    m = min(50, len(ref.history), len(info.history), len(hs))
+    d = np.abs(info.history[:m] - ref.history[:m]) / ref.history[:m]
+    assert np.all(d <= np.maximum(1e-9, 100 * np.maximum.accumulate(hs[:m]))), (d.max(), hs[:m].max())
+    assert err <= max(1e-10, 100 * xs), (err, xs)
+    assert info.rel_res_true < 2e-8
+
+
+@pytest.mark.parametrize("k,method", [(k, m) for k in (1, 2, 4) for m in METHODS])
+def test_fixed_iterations_match_oracle(pkg, ctx, k, method):
+    """Same number of iterations on both sides: the iterates agree to 1e-10."""
+    Acsr, B, name = _problem(k)
+    it = 8
+    ref = O.solve(Acsr, B, method, tol=0.0, maxit=it)
+    xs, hs, _ = _self_sensitivity(Acsr, B, method, ref, tol=0.0, maxit=it)
+    A = pkg.Matrix.from_csr(ctx, Acsr)
+    X, info = pkg.solve(ctx, A, B, method, tol=0.0, maxit=it)
+    A.close()
+    assert info.iterations == it and info.status == ref.status
+    # 1e-10, or 100x the oracle's own spread where the recurrence amplifies
+    # rounding faster (Bl-BiCG-rQ on the convection-dominated 3D problem)
+    assert _rel(X, ref.X) < max(1e-10, 100 * xs), (_rel(X, ref.X), xs)
+    np.testing.assert_allclose(info.history, ref.history, rtol=max(1e-10, 100 * hs.max()), atol=0)
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_adjoint_solve(pkg, ctx, method):
+    Acsr, B, name = _problem(4)
+    At = Acsr.to_scipy().conj().T.tocsr()
+    ref = O.solve(At, B, method, tol=1e-8, maxit=3000)
+    A = pkg.Matrix.from_csr(ctx, Acsr)
+    X, info = pkg.solve(ctx, A, B, method, tol=1e-8, maxit=3000, adjoint=True)
+    A.close()
+    assert info.status == 0 and abs(info.iterations - ref.iterations) <= max(1, int(0.05 * ref.iterations))
+    assert _rel(X, ref.X) < 1e-6
+
+
+@pytest.mark.parametrize("method", ["egl_bicg", "gl_bicgstab", "bl_bicgstab_rq"])
+@pytest.mark.parametrize("k", [2, 4, 5])
+def test_mixed_precision_refinement(pkg, ctx, k, method):
+    Acsr, B, name = _problem(k)
+    say("mixed", name, method)
+    ref = O.solve(Acsr, B, method, tol=1e-12, maxit=5000)
+    A = pkg.Matrix.from_csr(ctx, Acsr)
+    X, info = pkg.solve(ctx, A, B, method, tol=1e-8, precision="fp32_refine", inner_tol=1e-4, max_outer=20)
+    A.close()
+    say(f"  status={info.status_name} outer={info.outer_iterations} inner_it={info.iterations} "
+        f"res={info.rel_res_true:.3e} err_vs_fp64_oracle={_rel(X, ref.X):.3e}")
+    assert info.status == 0 and info.rel_res_true <= 1e-8
+    assert _rel(X, ref.X) < 1e-6
+
+
+def test_sell_solve_matches_csr(pkg, ctx):
+    Acsr, B, name = _problem(4)
+    A1 = pkg.Matrix.from_csr(ctx, Acsr)
+    A2 = pkg.Matrix.from_csr(ctx, Acsr, fmt="sell", sell_C=32, sell_sigma=256)
+    for method in ("egl_bicg", "bl_bicgstab_rq"):
+        X1, i1 = pkg.solve(ctx, A1, B, method)
+        X2, i2 = pkg.solve(ctx, A2, B, method)
+        assert i1.iterations == i2.iterations
+        assert _rel(X2, X1) < 1e-10
+    assert A2.sell_padding >= 1.0
+    A1.close(); A2.close()
+
+
+# ---------------------------------------------------------------- failure paths
+def test_breakdown_zero_mean_shadow(pkg, ctx):
+    C = I.convdiff2d(8)
+    b = I.gaussian_block(C.n, 1, seed=18)
+    B = np.hstack([b, -b])
+    A = pkg.Matrix.from_csr(ctx, C)
+    X, info = pkg.solve(ctx, A, B, "egl_bicg", preprocess_qr=False)
+    assert info.status_name == "breakdown" and info.breakdown_iter == 0
+    assert np.all(X == 0)
+    A.close()
+
+
+def test_not_converged_returns_last_iterate(pkg, ctx):
+    C = I.convdiff2d(12)
+    B = I.gaussian_block(C.n, 2, seed=21)
+    ref = O.solve(C, B, "gl_bicg", tol=1e-8, maxit=3)
+    A = pkg.Matrix.from_csr(ctx, C)
+    X, info = pkg.solve(ctx, A, B, "gl_bicg", tol=1e-8, maxit=3)
+    assert info.status_name == "not_converged" and info.iterations == 3 and len(info.history) == 4
+    assert _rel(X, ref.X) < 1e-12
+    A.close()
+
+
+def test_nan_input_rejected(pkg, ctx):
+    C = I.convdiff2d(8)
+    B = I.gaussian_block(C.n, 2, seed=1)
+    B[3, 1] = np.nan
+    A = pkg.Matrix.from_csr(ctx, C)
+    with pytest.raises(pkg.SkrError):
+        pkg.solve(ctx, A, B, "gl_bicg")
+    A.close()
+
+
+def test_warm_start(pkg, ctx):
+    C = I.convdiff2d(16)
+    B = I.gaussian_block(C.n, 3, seed=2)
+    A = pkg.Matrix.from_csr(ctx, C)
+    X1, i1 = pkg.solve(ctx, A, B, "egl_bicg", tol=1e-4)
+    X2, i2 = pkg.solve(ctx, A, B, "egl_bicg", X=X1.copy(), tol=1e-6)
+    ref = O.solve(C, B, "egl_bicg", tol=1e-6, X0=X1)
+    assert i2.status == 0 and abs(i2.iterations - ref.iterations) <= max(1, int(0.05 * ref.iterations))
+    assert _rel(X2, ref.X) < 1e-8
+    A.close()
+
+
+def test_graph_and_eager_agree(pkg, ctx):
+    Acsr, B, name = _problem(2)
+    A = pkg.Matrix.from_csr(ctx, Acsr)
+    for method in ("egl_qmr", "bl_bicg_rq"):
+        X1, i1 = pkg.solve(ctx, A, B, method, use_graph=True)
+        X2, i2 = pkg.solve(ctx, A, B, method, use_graph=False)
+        X3, i3 = pkg.solve(ctx, A, B, method, use_graph=True)   # cached graph replay
+        assert i1.iterations == i2.iterations == i3.iterations
+        assert np.array_equal(X1, X2) and np.array_equal(X1, X3)
+    A.close()
