@@ -91,6 +91,9 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--spmm-only", action="store_true",
+                    help="only the sparse x block kernel and a plain device copy of one block "
+                         "(the workload of the hardware-counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is "
@@ -113,6 +116,14 @@ def main():
     ctx = pkg.Context(0, stream=stream.cuda_stream)
     A = pkg.Matrix.from_csr(ctx, A_csr)
     B = torch.from_numpy(B_np).cuda()
+    if args.spmm_only:
+        roof = spmm_roofline(pkg, ctx, A, n, nnz, s, stream, reps=20)
+        C = torch.empty_like(B)
+        for _ in range(20):     # plain copy of one n x s block: calibration of the traffic counters
+            C.copy_(B)
+        torch.cuda.synchronize()
+        print(json.dumps({"spmm": roof, "copy_bytes_per_launch": 2 * B.numel() * 8}), flush=True)
+        return
     Xs = {m: torch.zeros_like(B) for m in METHODS}
     torch.cuda.synchronize()
 

@@ -10,16 +10,20 @@
 // same pass that produces their operands.
 //
 // Thin QR (Section 4: R = Q C with Q^H Q = I) is CholeskyQR2: G = Z^H Z = S1^H S1,
-// Q1 = Z S1^{-1}, G1 = Q1^H Q1 = S2^H S2, Q = Z (S2 S1)^{-1}, C = S2 S1.  If the
+// Q1 = Z S1^{-1}, G1 = Q1^H Q1 = S2^H S2, Q = Q1 S2^{-1}, C = S2 S1.  If the
 // first Cholesky factorisation fails, the first pass is repeated with the shift
 // 11 (n s + s(s+1)) u tr(G) (shifted CholeskyQR, Fukaya et al. 2020) and one
 // more unshifted pass is added (CholeskyQR3).  Q1 is never stored: each pass
-// recomputes it from Z.
+// recomputes the rows Z S1^{-1} S2^{-1} ... with the same sequence of row x
+// triangle products, so every Gram matrix is taken from exactly the rows the
+// next factor corrects.
 #pragma once
 
 #include "common.hpp"
 #include "glk.hpp"
 #include "small.hpp"
+
+#include <type_traits>
 
 namespace skr {
 
@@ -28,8 +32,8 @@ namespace skr {
 // (slot k at mats + k*s*s, complex FP64).
 enum {
     M_C = 0, M_CH, M_M, M_G, M_ALPHA, M_ALPHAH, M_ALPHAC, M_BETA, M_BETAH,
-    M_S1, M_S1INV, M_S12, M_S12INV, M_S, M_SINV,          // QR slot 0 work
-    M_T1, M_T1INV, M_T12, M_T12INV, M_T, M_TINV,          // QR slot 1 work
+    M_S1, M_S1INV, M_S12, M_S2INV, M_S, M_S3INV,          // QR slot 0 work (M_S: R factor)
+    M_T1, M_T1INV, M_T12, M_T2INV, M_T, M_T3INV,          // QR slot 1 work (M_T: R factor)
     M_N, M_A, M_AC, M_WC, M_B, M_RB, M_TMP,
     M_COUNT
 };
@@ -46,51 +50,145 @@ struct Tile16 {
     const int r1_ = min((tl).n, r0_ + (tl).rpc);                                       \
     for (int base_ = r0_; base_ < r1_; base_ += 16)
 
+// Row passes handled together by one lane group in the streaming block kernels
+// (their loads are issued before any is used, to keep loads in flight).
+template <class T, int J> struct RowPasses { static constexpr int value = Tr<T>::cplx ? (J == 1 ? 2 : 1) : (J == 1 ? 4 : 2); };
+
+#define SKR_TILE_LOOP_RP(tl, RP)                                                       \
+    const int lane = threadIdx.x & 15;                                                 \
+    const int grp = threadIdx.x >> 4;                                                  \
+    const int r0_ = xcd_chunk(blockIdx.x, gridDim.x) * (tl).rpc;                       \
+    const int r1_ = min((tl).n, r0_ + (tl).rpc);                                       \
+    for (int base_ = r0_; base_ < r1_; base_ += 16 * (RP))
+
+// FP64 value type of the block kernels: double for real storage, c64 for complex.
+template <class T> struct VT { using type = c64; };
+template <> struct VT<double> { using type = double; };
+template <> struct VT<float> { using type = double; };
+template <class T> using Val = typename VT<T>::type;
+
+__device__ inline double vup(double a) { return a; }
+__device__ inline double vup(float a) { return (double)a; }
+__device__ inline c64 vup(c64 a) { return a; }
+__device__ inline c64 vup(c32 a) { return up(a); }
+template <class T> __device__ inline T vdown(double v);
+template <> __device__ inline double vdown<double>(double v) { return v; }
+template <> __device__ inline float vdown<float>(double v) { return (float)v; }
+template <class T> __device__ inline T vdown(c64 v) { return down<T>(v); }
+template <class Vt> __device__ inline Vt vzero();
+template <> __device__ inline double vzero<double>() { return 0.0; }
+template <> __device__ inline c64 vzero<c64>() { return {0.0, 0.0}; }
+__device__ inline double vfma(double a, double b, double c) { return fma(a, b, c); }
+__device__ inline c64 vfma(c64 a, c64 b, c64 c) {
+    return {fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y))};
+}
+__device__ inline double vmul(c64 a, double b) { return a.x * b; }
+__device__ inline c64 vmul(c64 a, c64 b) { return a * b; }
+__device__ inline double vfrom(c64 a, double) { return a.x; }
+__device__ inline c64 vfrom(c64 a, c64) { return a; }
+
+// Loads are unconditional (row 0 / column s-1 stand in for out-of-range
+// positions) and the value is zeroed afterwards, so no branch separates them.
 template <class T, int J>
-__device__ inline void load_row(const T* __restrict__ P, int i, bool valid, int lane, int s, c64 (&v)[J]) {
+__device__ inline void load_row(const T* P, int i, bool valid, int lane, int s, Val<T> (&v)[J]) {
+    const size_t ib = (size_t)(valid ? i : 0) * s;
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-        int c = lane + 16 * j;
-        v[j] = (valid && c < s) ? up(P[(size_t)i * s + c]) : c64{0.0, 0.0};
+        const int c = lane + 16 * j;
+        const Val<T> x = vup(P[ib + min(c, s - 1)]);
+        v[j] = (valid && c < s) ? x : vzero<Val<T>>();
     }
 }
 template <class T, int J>
-__device__ inline void store_row(T* __restrict__ P, int i, bool valid, int lane, int s, const c64 (&v)[J]) {
+__device__ inline void store_row(T* P, int i, bool valid, int lane, int s, const Val<T> (&v)[J]) {
     if (!valid) return;
 #pragma unroll
     for (int j = 0; j < J; ++j) {
         int c = lane + 16 * j;
-        if (c < s) P[(size_t)i * s + c] = down<T>(v[j]);
+        if (c < s) P[(size_t)i * s + c] = vdown<T>(v[j]);
     }
 }
 // tile[grp][:] = v (this lane's entries)
-template <int J>
-__device__ inline void put_tile(c64* tile, int grp, int lane, int s, const c64 (&v)[J]) {
+template <class Vt, int J>
+__device__ inline void put_tile(Vt* tile, int grp, int lane, int s, const Vt (&v)[J]) {
 #pragma unroll
     for (int j = 0; j < J; ++j) {
         int c = lane + 16 * j;
         if (c < s) tile[grp * s + c] = v[j];
     }
 }
-// out[j] (+)= sum_a tile[grp][a] * M[a][c_j]
-template <int J>
-__device__ inline void tile_times(const c64* tile, const c64* M, int grp, int lane, int s, c64 (&out)[J]) {
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-        int c = lane + 16 * j;
-        if (c >= s) continue;
-        c64 acc = out[j];
-        for (int a = 0; a < s; ++a) {
-            c64 t = tile[grp * s + a], m = M[a * s + c];
-            acc.x = fma(t.x, m.x, fma(-t.y, m.y, acc.x));
-            acc.y = fma(t.x, m.y, fma(t.y, m.x, acc.y));
-        }
-        out[j] = acc;
+// an s x s FP64 coefficient matrix (complex FP64 in device memory) copied into LDS
+template <class Vt>
+__device__ inline void lds_load_mat(Vt* dst, const c64* __restrict__ src, int s) {
+    for (int e = threadIdx.x; e < s * s; e += kBlock) dst[e] = vfrom(src[e], Vt{});
+}
+
+// Broadcast of lane N of each 16-lane row (DPP row_newbcast, gfx90a and later):
+// inside a tile-16 row group this hands every lane the row's entry of column N
+// without LDS or a barrier.
+template <int N>
+__device__ inline double rbc(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), 0x150 + N, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x150 + N, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, (long long)(unsigned)lo | ((long long)hi << 32));
+}
+template <int N>
+__device__ inline c64 rbc(c64 v) { return {rbc<N>(v.x), rbc<N>(v.y)}; }
+
+template <int A, int END, class F>
+__device__ inline void static_for(F&& f) {
+    if constexpr (A < END) {
+        f(std::integral_constant<int, A>{});
+        static_for<A + 1, END>(f);
     }
 }
-__device__ inline void lds_load_mat(c64* dst, const c64* __restrict__ src, int s) {
-    for (int e = threadIdx.x; e < s * s; e += kBlock) dst[e] = src[e];
-}
+
+// Row x coefficient matrix: out[j] += sum_a x_a M[a][lane + 16 j], where x_a is
+// column a of this lane's row, held by lane a % 16 of the row group in
+// register a / 16 (padding columns are zero).  Real blocks with s <= 16 keep
+// this lane's column of M in registers; otherwise M is read from LDS.  Output
+// padding columns are set to zero.
+template <class T, int J>
+struct Coef {
+    using VV = Val<T>;
+    static constexpr bool REG = !Tr<T>::cplx && J == 1;
+    double m[REG ? 16 : 1];
+    const VV* M;
+    int s;
+    __device__ inline void load(const VV* Mlds, int s_, int lane) {
+        M = Mlds;
+        s = s_;
+        if constexpr (REG) {
+#pragma unroll
+            for (int a = 0; a < 16; ++a) m[a] = (a < s && lane < s) ? (double)Mlds[a * s + lane] : 0.0;
+        }
+    }
+    __device__ inline void apply(const VV (&x)[J], int lane, VV (&out)[J]) const {
+        if constexpr (REG) {
+            double acc = out[0];
+            static_for<0, 16>([&](auto ic) {
+                constexpr int a = decltype(ic)::value;
+                acc = fma(rbc<a>(x[0]), m[a], acc);
+            });
+            out[0] = acc;
+        } else {
+            int cc[J];
+#pragma unroll
+            for (int j = 0; j < J; ++j) cc[j] = min(lane + 16 * j, s - 1);
+            static_for<0, 16 * J>([&](auto ic) {
+                constexpr int a = decltype(ic)::value;
+                const VV xa = rbc<a % 16>(x[a / 16]);
+                const int ar = min(a, s - 1) * s;
+#pragma unroll
+                for (int j = 0; j < J; ++j) out[j] = vfma(xa, M[ar + cc[j]], out[j]);
+            });
+#pragma unroll
+            for (int j = 0; j < J; ++j)
+                if (lane + 16 * j >= s) out[j] = vzero<VV>();
+        }
+    }
+};
 
 // ---------------------------------------------------------------- Gram
 // part[b] = L^H R over this workgroup's rows
@@ -98,15 +196,19 @@ template <class T, int J>
 __global__ __launch_bounds__(kBlock) void k_bl_gram(const Ctl* ctl, Tile16 tl, const T* __restrict__ Lm,
                                                     const T* __restrict__ Rm, c64* part) {
     if (stopped(ctl)) return;
+    constexpr int RP = RowPasses<T, J>::value;
     GramAcc<J, Tr<T>::cplx> g;
     g.clear();
-    SKR_TILE_LOOP(tl) {
-        const int i = base_ + grp;
-        const bool valid = i < r1_;
-        c64 l[J], r[J];
-        load_row<T, J>(Lm, i, valid, lane, tl.s, l);
-        load_row<T, J>(Rm, i, valid, lane, tl.s, r);
-        g.add(l, r);
+    SKR_TILE_LOOP_RP(tl, RP) {
+        Val<T> l[RP][J], r[RP][J];
+#pragma unroll
+        for (int p = 0; p < RP; ++p) {
+            const int i = base_ + 16 * p + grp;
+            load_row<T, J>(Lm, i, i < r1_, lane, tl.s, l[p]);
+            load_row<T, J>(Rm, i, i < r1_, lane, tl.s, r[p]);
+        }
+#pragma unroll
+        for (int p = 0; p < RP; ++p) g.add(l[p], r[p]);
     }
     __shared__ c64 lds[(16 * J) * (16 * J)];
     g.store(tl.s, lds, part + (size_t)blockIdx.x * tl.s * tl.s);
@@ -121,14 +223,21 @@ __global__ __launch_bounds__(kBlock) void k_reduce_parts(const Ctl* ctl, int con
     if (e >= E) return;
     const int per = (np + gridDim.y - 1) / gridDim.y;
     const int b0 = blockIdx.y * per, b1 = min(np, b0 + per);
-    c64 acc = {0.0, 0.0};
-    for (int b = b0; b < b1; ++b) acc = acc + part[(size_t)b * E + e];
-    out[(size_t)blockIdx.y * E + e] = acc;
+    c64 a0 = {0.0, 0.0}, a1 = {0.0, 0.0}, a2 = {0.0, 0.0}, a3 = {0.0, 0.0};
+    int b = b0;
+    for (; b + 4 <= b1; b += 4) {
+        a0 = a0 + part[(size_t)b * E + e];
+        a1 = a1 + part[(size_t)(b + 1) * E + e];
+        a2 = a2 + part[(size_t)(b + 2) * E + e];
+        a3 = a3 + part[(size_t)(b + 3) * E + e];
+    }
+    for (; b < b1; ++b) a0 = a0 + part[(size_t)b * E + e];
+    out[(size_t)blockIdx.y * E + e] = (a0 + a1) + (a2 + a3);
 }
 
 // final sum of the stage-2 partials into LDS
 __device__ inline void gram_final(const c64* __restrict__ part2, int p2, int E, c64* dst) {
-    for (int e = threadIdx.x; e < E; e += kBlock) {
+    for (int e = threadIdx.x; e < E; e += blockDim.x) {
         c64 acc = part2[e];
         for (int y = 1; y < p2; ++y) acc = acc + part2[(size_t)y * E + e];
         dst[e] = acc;
@@ -139,43 +248,81 @@ __device__ inline void gram_final(const c64* __restrict__ part2, int p2, int E, 
 // ---------------------------------------------------------------- triangular pass
 enum { TRI_WRITE = 1, TRI_G_OUT_OUT = 2, TRI_G_OTHER_OUT = 4, TRI_G_OUT_OTHER = 8 };
 
-// out = Z * Minv (Minv at mats slot `minv`).  cond_slot >= 0: run only when the
-// shifted first pass was used for that QR slot.
+// out = Z S1^{-1} S2^{-1} [S3^{-1}]: the first `nchain` inverse factors of QR
+// slot `slot`, applied one after the other, plus S3^{-1} when `add_shift` and
+// the slot used the shifted first pass.  cond: run only when the shifted pass
+// was used.  Out may alias Z (each row is read before it is written, by the
+// same lanes).
 template <class T, int J>
-__global__ __launch_bounds__(kBlock) void k_bl_tri(const Ctl* ctl, int cond_slot, Tile16 tl, int mode,
-                                                   const c64* __restrict__ mats, int minv, const T* Z, T* Out,
-                                                   const T* __restrict__ Other, c64* part) {
+__global__ __launch_bounds__(kBlock) void k_bl_tri(const Ctl* ctl, int slot, int cond, int nchain, int add_shift,
+                                                   Tile16 tl, int mode, const c64* __restrict__ mats, const T* Z,
+                                                   T* Out, const T* __restrict__ Other, c64* part) {
     if (stopped(ctl)) return;
-    if (cond_slot >= 0 && !ctl->qr_shift[cond_slot]) return;
+    const int shifted = ctl->qr_shift[slot];
+    if (cond && !shifted) return;
+    constexpr int RP = RowPasses<T, J>::value;
+    const int nc = nchain + (add_shift && shifted ? 1 : 0);
     extern __shared__ c64 dyn[];
-    const int s = tl.s;
-    c64* M = dyn;                 // s*s
-    c64* tile = dyn + s * s;      // 16*s
-    lds_load_mat(M, mats + (size_t)minv * s * s, s);
+    using VV = Val<T>;
+    const int s = tl.s, ss = s * s;
+    const int base = slot == 0 ? M_S1 : M_T1;
+    VV* M = reinterpret_cast<VV*>(dyn);   // up to 3 matrices
+    lds_load_mat(M, mats + (size_t)(base + 1) * ss, s);
+    if (nc > 1) lds_load_mat(M + ss, mats + (size_t)(base + 3) * ss, s);
+    if (nc > 2) lds_load_mat(M + 2 * ss, mats + (size_t)(base + 5) * ss, s);
+    __syncthreads();
+    const int ln = threadIdx.x & 15;
+    Coef<T, J> cf0, cf1, cf2;
+    cf0.load(M, s, ln);
+    if (nc > 1) cf1.load(M + ss, s, ln);
+    if (nc > 2) cf2.load(M + 2 * ss, s, ln);
     GramAcc<J, Tr<T>::cplx> g;
     g.clear();
-    SKR_TILE_LOOP(tl) {
-        const int i = base_ + grp;
-        const bool valid = i < r1_;
-        c64 z[J], o[J];
-        load_row<T, J>(Z, i, valid, lane, s, z);
-        __syncthreads();
-        put_tile<J>(tile, grp, lane, s, z);
-        __syncthreads();
+    SKR_TILE_LOOP_RP(tl, RP) {
+        VV o[RP][J];
 #pragma unroll
-        for (int j = 0; j < J; ++j) o[j] = {0.0, 0.0};
-        tile_times<J>(tile, M, grp, lane, s, o);
-        if (!valid) {
-#pragma unroll
-            for (int j = 0; j < J; ++j) o[j] = {0.0, 0.0};
+        for (int p = 0; p < RP; ++p) {
+            const int i = base_ + 16 * p + grp;
+            load_row<T, J>(Z, i, i < r1_, lane, s, o[p]);
         }
-        if (mode & TRI_WRITE) store_row<T, J>(Out, i, valid, lane, s, o);
-        if (mode & TRI_G_OUT_OUT) g.add(o, o);
-        if (mode & (TRI_G_OTHER_OUT | TRI_G_OUT_OTHER)) {
-            c64 ot[J];
-            load_row<T, J>(Other, i, valid, lane, s, ot);
-            if (mode & TRI_G_OTHER_OUT) g.add(ot, o);
-            else g.add(o, ot);
+#pragma unroll
+        for (int p = 0; p < RP; ++p) {
+            VV t[J];
+#pragma unroll
+            for (int j = 0; j < J; ++j) t[j] = vzero<VV>();
+            cf0.apply(o[p], lane, t);
+            if (nc > 1) {
+#pragma unroll
+                for (int j = 0; j < J; ++j) o[p][j] = vzero<VV>();
+                cf1.apply(t, lane, o[p]);
+                if (nc > 2) {
+#pragma unroll
+                    for (int j = 0; j < J; ++j) t[j] = vzero<VV>();
+                    cf2.apply(o[p], lane, t);
+#pragma unroll
+                    for (int j = 0; j < J; ++j) o[p][j] = t[j];
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < J; ++j) o[p][j] = t[j];
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < RP; ++p) {
+            const int i = base_ + 16 * p + grp;
+            const bool valid = i < r1_;
+            if (!valid) {
+#pragma unroll
+                for (int j = 0; j < J; ++j) o[p][j] = vzero<VV>();
+            }
+            if (mode & TRI_WRITE) store_row<T, J>(Out, i, valid, lane, s, o[p]);
+            if (mode & TRI_G_OUT_OUT) g.add(o[p], o[p]);
+            if (mode & (TRI_G_OTHER_OUT | TRI_G_OUT_OTHER)) {
+                VV ot[J];
+                load_row<T, J>(Other, i, valid, lane, s, ot);
+                if (mode & TRI_G_OTHER_OUT) g.add(ot, o[p]);
+                else g.add(o[p], ot);
+            }
         }
     }
     if (mode & (TRI_G_OUT_OUT | TRI_G_OTHER_OUT | TRI_G_OUT_OTHER)) {
@@ -190,41 +337,50 @@ __global__ __launch_bounds__(kBlock) void k_bl_axpm(const Ctl* ctl, Tile16 tl, c
                                                     const c64* __restrict__ sc, int gslot, const T* A,
                                                     const T* B, const T* __restrict__ Cm, T* Out, c64* part) {
     if (stopped(ctl)) return;
+    constexpr int RP = RowPasses<T, J>::value;
     extern __shared__ c64 dyn[];
+    using VV = Val<T>;
     const int s = tl.s;
-    c64* M = dyn;
-    c64* tile = dyn + s * s;
+    VV* M = reinterpret_cast<VV*>(dyn);
     lds_load_mat(M, mats + (size_t)mslot * s * s, s);
-    const c64 gamma = Cm ? sc[gslot] : c64{0.0, 0.0};
+    __syncthreads();
+    Coef<T, J> cf;
+    cf.load(M, s, threadIdx.x & 15);
+    const VV gamma = Cm ? vfrom(sc[gslot], VV{}) : vzero<VV>();
     GramAcc<J, Tr<T>::cplx> g;
     g.clear();
-    SKR_TILE_LOOP(tl) {
-        const int i = base_ + grp;
-        const bool valid = i < r1_;
-        c64 b[J], o[J];
-        load_row<T, J>(B, i, valid, lane, s, b);
-        if (Cm) {
-            c64 cc[J];
-            load_row<T, J>(Cm, i, valid, lane, s, cc);
+    SKR_TILE_LOOP_RP(tl, RP) {
+        VV b[RP][J], o[RP][J];
 #pragma unroll
-            for (int j = 0; j < J; ++j) b[j] = b[j] + gamma * cc[j];
-        }
-        if (A) load_row<T, J>(A, i, valid, lane, s, o);
-        else {
+        for (int p = 0; p < RP; ++p) {
+            const int i = base_ + 16 * p + grp;
+            const bool valid = i < r1_;
+            load_row<T, J>(B, i, valid, lane, s, b[p]);
+            if (Cm) {
+                VV cc[J];
+                load_row<T, J>(Cm, i, valid, lane, s, cc);
 #pragma unroll
-            for (int j = 0; j < J; ++j) o[j] = {0.0, 0.0};
-        }
-        __syncthreads();
-        put_tile<J>(tile, grp, lane, s, b);
-        __syncthreads();
-        tile_times<J>(tile, M, grp, lane, s, o);
-        store_row<T, J>(Out, i, valid, lane, s, o);
-        if (GRAM) {
-            if (!valid) {
-#pragma unroll
-                for (int j = 0; j < J; ++j) o[j] = {0.0, 0.0};
+                for (int j = 0; j < J; ++j) b[p][j] = vfma(gamma, cc[j], b[p][j]);
             }
-            g.add(o, o);
+            if (A) load_row<T, J>(A, i, valid, lane, s, o[p]);
+            else {
+#pragma unroll
+                for (int j = 0; j < J; ++j) o[p][j] = vzero<VV>();
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < RP; ++p) {
+            const int i = base_ + 16 * p + grp;
+            const bool valid = i < r1_;
+            cf.apply(b[p], lane, o[p]);
+            store_row<T, J>(Out, i, valid, lane, s, o[p]);
+            if (GRAM) {
+                if (!valid) {
+#pragma unroll
+                    for (int j = 0; j < J; ++j) o[p][j] = vzero<VV>();
+                }
+                g.add(o[p], o[p]);
+            }
         }
     }
     if (GRAM) {
@@ -233,45 +389,48 @@ __global__ __launch_bounds__(kBlock) void k_bl_axpm(const Ctl* ctl, Tile16 tl, c
     }
 }
 
-// Bl-BiCG-rQ: X += V (alpha C); Z = Q - W alpha; part = Z^H Z
+// Bl-BiCG-rQ: X += V (alpha C); Z = Q - W alpha; part = Z^H Z.  mats holds -alpha.
 template <class T, int J>
 __global__ __launch_bounds__(kBlock) void k_blrq_updz(const Ctl* ctl, Tile16 tl, const c64* __restrict__ mats,
-                                                      T* __restrict__ X, const T* __restrict__ V,
+                                                      T* __restrict__ X, const T* __restrict__ Vb,
                                                       const T* __restrict__ Q, const T* __restrict__ W,
                                                       T* __restrict__ Z, c64* part) {
     if (stopped(ctl)) return;
+    constexpr int RP = RowPasses<T, J>::value;
     extern __shared__ c64 dyn[];
+    using VV = Val<T>;
     const int s = tl.s;
-    c64* Ma = dyn;                  // alpha
-    c64* Mac = dyn + s * s;         // alpha C
-    c64* tv = dyn + 2 * s * s;      // V tile
-    c64* tw = tv + 16 * s;          // W tile
+    VV* Ma = reinterpret_cast<VV*>(dyn);  // -alpha
+    VV* Mac = Ma + s * s;                 // alpha C
     lds_load_mat(Ma, mats + (size_t)M_ALPHA * s * s, s);
     lds_load_mat(Mac, mats + (size_t)M_ALPHAC * s * s, s);
+    __syncthreads();
+    Coef<T, J> ca, cac;
+    ca.load(Ma, s, threadIdx.x & 15);
+    cac.load(Mac, s, threadIdx.x & 15);
     GramAcc<J, Tr<T>::cplx> g;
     g.clear();
-    SKR_TILE_LOOP(tl) {
-        const int i = base_ + grp;
-        const bool valid = i < r1_;
-        c64 v[J], w[J], x[J], z[J];
-        load_row<T, J>(V, i, valid, lane, s, v);
-        load_row<T, J>(W, i, valid, lane, s, w);
-        load_row<T, J>(X, i, valid, lane, s, x);
-        load_row<T, J>(Q, i, valid, lane, s, z);
-        __syncthreads();
-        put_tile<J>(tv, grp, lane, s, v);
-        put_tile<J>(tw, grp, lane, s, w);
-        __syncthreads();
-        tile_times<J>(tv, Mac, grp, lane, s, x);
-        c64 wa[J];
+    SKR_TILE_LOOP_RP(tl, RP) {
+        VV v[RP][J], w[RP][J], x[RP][J], z[RP][J];
 #pragma unroll
-        for (int j = 0; j < J; ++j) wa[j] = {0.0, 0.0};
-        tile_times<J>(tw, Ma, grp, lane, s, wa);
+        for (int p = 0; p < RP; ++p) {
+            const int i = base_ + 16 * p + grp;
+            const bool valid = i < r1_;
+            load_row<T, J>(Vb, i, valid, lane, s, v[p]);
+            load_row<T, J>(W, i, valid, lane, s, w[p]);
+            load_row<T, J>(X, i, valid, lane, s, x[p]);
+            load_row<T, J>(Q, i, valid, lane, s, z[p]);
+        }
 #pragma unroll
-        for (int j = 0; j < J; ++j) z[j] = valid ? z[j] + wa[j] : c64{0.0, 0.0};  // mats holds -alpha
-        store_row<T, J>(X, i, valid, lane, s, x);
-        store_row<T, J>(Z, i, valid, lane, s, z);
-        g.add(z, z);
+        for (int p = 0; p < RP; ++p) {
+            const int i = base_ + 16 * p + grp;
+            const bool valid = i < r1_;
+            cac.apply(v[p], lane, x[p]);
+            ca.apply(w[p], lane, z[p]);
+            store_row<T, J>(X, i, valid, lane, s, x[p]);
+            store_row<T, J>(Z, i, valid, lane, s, z[p]);
+            g.add(z[p], z[p]);
+        }
     }
     __syncthreads();
     g.store(s, dyn, part + (size_t)blockIdx.x * s * s);
@@ -284,36 +443,45 @@ __global__ __launch_bounds__(kBlock) void k_blst_upd(const Ctl* ctl, Tile16 tl, 
                                                      const T* __restrict__ U, const T* __restrict__ St,
                                                      const T* __restrict__ Tt, T* __restrict__ Z, c64* part) {
     if (stopped(ctl)) return;
+    constexpr int RP = RowPasses<T, J>::value;
     extern __shared__ c64 dyn[];
+    using VV = Val<T>;
     const int s = tl.s;
-    c64* Mac = dyn;                 // a C
-    c64* Mwc = dyn + s * s;         // omega C
-    c64* tu = dyn + 2 * s * s;
-    c64* ts = tu + 16 * s;
+    VV* Mac = reinterpret_cast<VV*>(dyn);  // a C
+    VV* Mwc = Mac + s * s;                 // omega C
     lds_load_mat(Mac, mats + (size_t)M_AC * s * s, s);
     lds_load_mat(Mwc, mats + (size_t)M_WC * s * s, s);
-    const c64 w = sc[SC_OMEGA];
+    __syncthreads();
+    Coef<T, J> cac, cwc;
+    cac.load(Mac, s, threadIdx.x & 15);
+    cwc.load(Mwc, s, threadIdx.x & 15);
+    const VV mw = vfrom(-sc[SC_OMEGA], VV{});
     GramAcc<J, Tr<T>::cplx> g;
     g.clear();
-    SKR_TILE_LOOP(tl) {
-        const int i = base_ + grp;
-        const bool valid = i < r1_;
-        c64 u[J], st[J], tt[J], x[J], z[J];
-        load_row<T, J>(U, i, valid, lane, s, u);
-        load_row<T, J>(St, i, valid, lane, s, st);
-        load_row<T, J>(Tt, i, valid, lane, s, tt);
-        load_row<T, J>(X, i, valid, lane, s, x);
-        __syncthreads();
-        put_tile<J>(tu, grp, lane, s, u);
-        put_tile<J>(ts, grp, lane, s, st);
-        __syncthreads();
-        tile_times<J>(tu, Mac, grp, lane, s, x);
-        tile_times<J>(ts, Mwc, grp, lane, s, x);
+    SKR_TILE_LOOP_RP(tl, RP) {
+        VV u[RP][J], st[RP][J], tt[RP][J], x[RP][J];
 #pragma unroll
-        for (int j = 0; j < J; ++j) z[j] = st[j] - w * tt[j];
-        store_row<T, J>(X, i, valid, lane, s, x);
-        store_row<T, J>(Z, i, valid, lane, s, z);
-        g.add(z, z);
+        for (int p = 0; p < RP; ++p) {
+            const int i = base_ + 16 * p + grp;
+            const bool valid = i < r1_;
+            load_row<T, J>(U, i, valid, lane, s, u[p]);
+            load_row<T, J>(St, i, valid, lane, s, st[p]);
+            load_row<T, J>(Tt, i, valid, lane, s, tt[p]);
+            load_row<T, J>(X, i, valid, lane, s, x[p]);
+        }
+#pragma unroll
+        for (int p = 0; p < RP; ++p) {
+            const int i = base_ + 16 * p + grp;
+            const bool valid = i < r1_;
+            cac.apply(u[p], lane, x[p]);
+            cwc.apply(st[p], lane, x[p]);
+            VV z[J];
+#pragma unroll
+            for (int j = 0; j < J; ++j) z[j] = vfma(mw, tt[p][j], st[p][j]);
+            store_row<T, J>(X, i, valid, lane, s, x[p]);
+            store_row<T, J>(Z, i, valid, lane, s, z);
+            g.add(z, z);
+        }
     }
     __syncthreads();
     g.store(s, dyn, part + (size_t)blockIdx.x * s * s);
@@ -323,11 +491,10 @@ __global__ __launch_bounds__(kBlock) void k_blst_upd(const Ctl* ctl, Tile16 tl, 
 // Dynamic LDS: 6 s x s matrices.
 __device__ inline void set_bd(Ctl* c) { set_breakdown(c); }
 
-// QR step 1 (or 3): G -> S1 (with shift fallback on the first pass), S1inv.
-// pass 1: reads the reduced Gram of Z; stores S1, S1INV of the slot.
-// pass 2: Gram of Q1 -> S2; S12 = S2 S1, S12inv = S1inv S2inv; if no shift was
-//         used these are the final factors (S, SINV).
-// pass 3 (only with shift): Gram of Q2 -> S3; S = S3 S12, SINV = S12inv S3inv.
+// CholeskyQR factor kernels for QR slot `slot` (reduced Gram in part2):
+// pass 1: G = Z^H Z -> S1 (shifted if the plain factorisation fails), S1^{-1};
+// pass 2: G = Q1^H Q1 -> S2, S2^{-1}; S12 = S2 S1, the R factor S = S12 unless shifted;
+// pass 3 (shifted case only): G = Q2^H Q2 -> S3, S3^{-1}; S = S3 S12.
 __global__ void k_qr_chol(Ctl* c, int slot, int pass, int n, int s, const c64* __restrict__ part2, int p2,
                           c64* __restrict__ mats) {
     if (stopped(c)) return;
@@ -343,9 +510,9 @@ __global__ void k_qr_chol(Ctl* c, int slot, int pass, int n, int s, const c64* _
     c64* mS1 = mats + (size_t)(base + 0) * ss;
     c64* mS1i = mats + (size_t)(base + 1) * ss;
     c64* mS12 = mats + (size_t)(base + 2) * ss;
-    c64* mS12i = mats + (size_t)(base + 3) * ss;
+    c64* mS2i = mats + (size_t)(base + 3) * ss;
     c64* mS = mats + (size_t)(base + 4) * ss;
-    c64* mSi = mats + (size_t)(base + 5) * ss;
+    c64* mS3i = mats + (size_t)(base + 5) * ss;
     gram_final(part2, p2, ss, G);
     if (pass == 1) {
         if (threadIdx.x == 0) c->qr_shift[slot] = 0;
@@ -365,7 +532,7 @@ __global__ void k_qr_chol(Ctl* c, int slot, int pass, int n, int s, const c64* _
             return;
         }
         sm_tri_inv_upper(A, B, s);
-        for (int e = threadIdx.x; e < ss; e += kBlock) {
+        for (int e = threadIdx.x; e < ss; e += blockDim.x) {
             mS1[e] = A[e];
             mS1i[e] = B[e];
         }
@@ -377,19 +544,15 @@ __global__ void k_qr_chol(Ctl* c, int slot, int pass, int n, int s, const c64* _
         if (threadIdx.x == 0) set_bd(c);
         return;
     }
-    sm_tri_inv_upper(A, B, s);  // B = S_k^{-1}
-    const c64* prevS = pass == 2 ? mS1 : mS12;
-    const c64* prevSi = pass == 2 ? mS1i : mS12i;
-    sm_copy(G, prevS, ss);
-    sm_gemm(D, A, 0, G, 0, s);   // S_k * prev
-    sm_copy(G, prevSi, ss);
-    sm_gemm(A, G, 0, B, 0, s);   // prev^{-1} S_k^{-1}
-    const bool final_ = (pass == 3) || !c->qr_shift[slot];
-    c64* oS = final_ ? mS : mS12;
-    c64* oSi = final_ ? mSi : mS12i;
-    for (int e = threadIdx.x; e < ss; e += kBlock) {
+    sm_tri_inv_upper(A, B, s);   // B = S_k^{-1}
+    sm_copy(G, pass == 2 ? mS1 : mS12, ss);
+    sm_gemm(D, A, 0, G, 0, s);   // S_k * (previous product)
+    c64* oS = (pass == 2 && c->qr_shift[slot]) ? mS12 : mS;
+    c64* oInv = pass == 2 ? mS2i : mS3i;
+    for (int e = threadIdx.x; e < ss; e += blockDim.x) {
         oS[e] = D[e];
-        oSi[e] = A[e];
+        oInv[e] = B[e];
+        if (pass == 2) mS12[e] = D[e];
     }
 }
 
@@ -413,7 +576,7 @@ __global__ void k_blrq_alpha(Ctl* c, int s, const c64* __restrict__ part2, int p
     const c64* Mm = mats + (size_t)M_M * ss;
     sm_copy(A, Mm, ss);
     sm_lu_solve(G, piv, A, s, s);                         // alpha
-    for (int e = threadIdx.x; e < ss; e += kBlock) {      // M^H
+    for (int e = threadIdx.x; e < ss; e += blockDim.x) {      // M^H
         int i = e / s, j = e - i * s;
         B[e] = conj_(Mm[j * s + i]);
     }
@@ -421,7 +584,7 @@ __global__ void k_blrq_alpha(Ctl* c, int s, const c64* __restrict__ part2, int p
     sm_lu_solve_h(G, piv, B, s, s);                       // alpha^
     sm_copy(D, mats + (size_t)M_C * ss, ss);
     sm_gemm(G, A, 0, D, 0, s);                            // alpha C (G reused)
-    for (int e = threadIdx.x; e < ss; e += kBlock) {
+    for (int e = threadIdx.x; e < ss; e += blockDim.x) {
         mats[(size_t)M_ALPHA * ss + e] = -A[e];           // stored negated: Z = Q + W (-alpha)
         mats[(size_t)M_ALPHAH * ss + e] = -B[e];
         mats[(size_t)M_ALPHAC * ss + e] = G[e];
@@ -443,20 +606,18 @@ __global__ void k_blrq_beta(Ctl* c, double* hist, int s, const c64* __restrict__
     c64* A = dyn + ss;
     c64* B = dyn + 2 * ss;
     c64* D = dyn + 3 * ss;
-    c64* E = dyn + 4 * ss;
     gram_final(part2, p2, ss, Mn);
-    // C = S C, C^ = S^ C^
+    // C = S C
     sm_copy(A, mats + (size_t)M_S * ss, ss);
     sm_copy(B, mats + (size_t)M_C * ss, ss);
     sm_gemm(D, A, 0, B, 0, s);
+    for (int e = threadIdx.x; e < ss; e += blockDim.x) mats[(size_t)M_C * ss + e] = D[e];
+    double res2 = sm_frob2(D, ss, &red);
+    // C^ = S^ C^
     sm_copy(A, mats + (size_t)M_T * ss, ss);
     sm_copy(B, mats + (size_t)M_CH * ss, ss);
-    sm_gemm(E, A, 0, B, 0, s);
-    for (int e = threadIdx.x; e < ss; e += kBlock) {
-        mats[(size_t)M_C * ss + e] = D[e];
-        mats[(size_t)M_CH * ss + e] = E[e];
-    }
-    double res2 = sm_frob2(D, ss, &red);
+    sm_gemm(D, A, 0, B, 0, s);
+    for (int e = threadIdx.x; e < ss; e += blockDim.x) mats[(size_t)M_CH * ss + e] = D[e];
     if (threadIdx.x == 0) flag = end_of_iteration(c, hist, res2) ? 1 : 0;
     __syncthreads();
     if (!flag) return;
@@ -470,12 +631,12 @@ __global__ void k_blrq_beta(Ctl* c, double* hist, int s, const c64* __restrict__
     sm_copy(B, mats + (size_t)M_T * ss, ss);   // S^
     sm_gemm(D, B, 1, Mn, 0, s);                // S^^H M'
     sm_lu_solve(A, piv, D, s, s);              // beta
+    for (int e = threadIdx.x; e < ss; e += blockDim.x) mats[(size_t)M_BETA * ss + e] = D[e];
     sm_copy(B, mats + (size_t)M_S * ss, ss);   // S
-    sm_gemm(E, B, 1, Mn, 1, s);                // S^H M'^H
-    sm_lu_solve_h(A, piv, E, s, s);            // beta^
-    for (int e = threadIdx.x; e < ss; e += kBlock) {
-        mats[(size_t)M_BETA * ss + e] = D[e];
-        mats[(size_t)M_BETAH * ss + e] = E[e];
+    sm_gemm(D, B, 1, Mn, 1, s);                // S^H M'^H
+    sm_lu_solve_h(A, piv, D, s, s);            // beta^
+    for (int e = threadIdx.x; e < ss; e += blockDim.x) {
+        mats[(size_t)M_BETAH * ss + e] = D[e];
         mats[(size_t)M_M * ss + e] = Mn[e];
     }
 }
@@ -492,10 +653,10 @@ __global__ void k_bl_init(Ctl* c, double* hist, int s, int copy_hat, const c64* 
     c64* G = dyn;
     if (p2 > 0) {
         gram_final(part2, p2, ss, G);
-        for (int e = threadIdx.x; e < ss; e += kBlock) mats[(size_t)gslot * ss + e] = G[e];
+        for (int e = threadIdx.x; e < ss; e += blockDim.x) mats[(size_t)gslot * ss + e] = G[e];
     }
     sm_copy(G, mats + (size_t)M_S * ss, ss);
-    for (int e = threadIdx.x; e < ss; e += kBlock) {
+    for (int e = threadIdx.x; e < ss; e += blockDim.x) {
         mats[(size_t)M_C * ss + e] = G[e];
         if (copy_hat) {
             mats[(size_t)M_CH * ss + e] = G[e];
@@ -533,12 +694,12 @@ __global__ void k_blst_a(Ctl* c, int s, const c64* __restrict__ part2, int p2, c
     }
     sm_copy(A, mats + (size_t)M_N * ss, ss);
     sm_lu_solve(G, piv, A, s, s);
-    for (int e = threadIdx.x; e < ss; e += kBlock) {
+    for (int e = threadIdx.x; e < ss; e += blockDim.x) {
         mats[(size_t)M_A * ss + e] = A[e];
         mats[(size_t)M_TMP * ss + e] = -A[e];
         mats[(size_t)M_G * ss + e] = G[e];
     }
-    for (int k = threadIdx.x; k < s; k += kBlock) sc[SC_PIV + k] = {(double)piv[k], 0.0};
+    for (int k = threadIdx.x; k < s; k += blockDim.x) sc[SC_PIV + k] = {(double)piv[k], 0.0};
 }
 
 // Bl-BiCGStab-rQ: (T~^H S~, T~^H T~) -> omega = tr(T~^H S~ K) / tr(T~^H T~ K), K = C C^H;
@@ -550,11 +711,10 @@ __global__ void k_blst_omega(Ctl* c, int s, const c64* __restrict__ part2, int p
     const int ss = s * s;
     c64* G1 = dyn;
     c64* G2 = dyn + ss;
-    c64* K = dyn + 2 * ss;
-    c64* A = dyn + 3 * ss;
-    c64* D = dyn + 4 * ss;
+    c64* A = dyn + 2 * ss;
+    c64* K = dyn + 3 * ss;
     // the two Grams are stored back to back: entries [0, ss) and [ss, 2 ss)
-    for (int e = threadIdx.x; e < 2 * ss; e += kBlock) {
+    for (int e = threadIdx.x; e < 2 * ss; e += blockDim.x) {
         c64 acc = part2[e];
         for (int y = 1; y < p2; ++y) acc = acc + part2[(size_t)y * 2 * ss + e];
         if (e < ss) G1[e] = acc;
@@ -579,9 +739,9 @@ __global__ void k_blst_omega(Ctl* c, int s, const c64* __restrict__ part2, int p
     __syncthreads();
     if (stopped(c)) return;
     const c64 w = sc[SC_OMEGA];
-    sm_copy(D, mats + (size_t)M_A * ss, ss);
-    sm_gemm(G1, D, 0, A, 0, s);                // a C
-    for (int e = threadIdx.x; e < ss; e += kBlock) {
+    sm_copy(G2, mats + (size_t)M_A * ss, ss);
+    sm_gemm(G1, G2, 0, A, 0, s);               // a C
+    for (int e = threadIdx.x; e < ss; e += blockDim.x) {
         mats[(size_t)M_AC * ss + e] = G1[e];
         mats[(size_t)M_WC * ss + e] = w * A[e];
     }
@@ -604,7 +764,7 @@ __global__ void k_blst_b(Ctl* c, double* hist, int s, const c64* __restrict__ pa
     sm_copy(A, mats + (size_t)M_S * ss, ss);
     sm_copy(B, mats + (size_t)M_C * ss, ss);
     sm_gemm(D, A, 0, B, 0, s);
-    for (int e = threadIdx.x; e < ss; e += kBlock) mats[(size_t)M_C * ss + e] = D[e];
+    for (int e = threadIdx.x; e < ss; e += blockDim.x) mats[(size_t)M_C * ss + e] = D[e];
     double res2 = sm_frob2(D, ss, &red);
     if (threadIdx.x == 0) flag = end_of_iteration(c, hist, res2) ? 1 : 0;
     __syncthreads();
@@ -616,11 +776,11 @@ __global__ void k_blst_b(Ctl* c, double* hist, int s, const c64* __restrict__ pa
         return;
     }
     sm_copy(A, mats + (size_t)M_G * ss, ss);
-    for (int k = threadIdx.x; k < s; k += kBlock) piv[k] = (int)sc[SC_PIV + k].x;
+    for (int k = threadIdx.x; k < s; k += blockDim.x) piv[k] = (int)sc[SC_PIV + k].x;
     sm_copy(B, Nn, ss);
     sm_lu_solve(A, piv, B, s, s);
     const c64 iw = cdiv(c64{1.0, 0.0}, w);
-    for (int e = threadIdx.x; e < ss; e += kBlock) {
+    for (int e = threadIdx.x; e < ss; e += blockDim.x) {
         mats[(size_t)M_B * ss + e] = iw * B[e];
         mats[(size_t)M_N * ss + e] = Nn[e];
     }

@@ -163,19 +163,22 @@ __device__ inline void block_reduce_store(c64 (&v)[K], c64* out) {
     }
 }
 
-// In a single workgroup: sum K values over `np` per-block partials laid out
-// [block][K]; result in res[0..K) (shared memory), visible after return.
+// In a single workgroup (any size that is a multiple of 64, at most 256): sum K
+// values over `np` per-block partials laid out [block][K]; result in res[0..K)
+// (shared memory), visible after return.  Fixed order: strided per thread,
+// butterfly within each wave, waves in order.
 template <int K>
 __device__ inline void sum_partials(const c64* __restrict__ part, int np, c64* res) {
     __shared__ c64 sm[kWaves][K];
     c64 v[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = {0.0, 0.0};
-    for (int b = threadIdx.x; b < np; b += kBlock) {
+    for (int b = threadIdx.x; b < np; b += blockDim.x) {
 #pragma unroll
         for (int k = 0; k < K; ++k) v[k] = v[k] + part[(size_t)b * K + k];
     }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nw = (blockDim.x + 63) >> 6;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         double a = wave_sum(v[k].x), b = wave_sum(v[k].y);
@@ -184,7 +187,7 @@ __device__ inline void sum_partials(const c64* __restrict__ part, int np, c64* r
     __syncthreads();
     if (threadIdx.x < K) {
         c64 t = sm[0][threadIdx.x];
-        for (int i = 1; i < kWaves; ++i) t = t + sm[i][threadIdx.x];
+        for (int i = 1; i < nw; ++i) t = t + sm[i][threadIdx.x];
         res[threadIdx.x] = t;
     }
     __syncthreads();
@@ -225,6 +228,13 @@ struct GramAcc {
                     im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-y[a].y, x[b].x, im[a][b], 0, 0, 0);
                 }
             }
+    }
+    // real operands
+    __device__ inline void add(const double (&y)[J], const double (&x)[J]) {
+#pragma unroll
+        for (int a = 0; a < J; ++a)
+#pragma unroll
+            for (int b = 0; b < J; ++b) re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(y[a], x[b], re[a][b], 0, 0, 0);
     }
     // Sum the 4 waves' partial Grams and write the s x s result (row-major,
     // G[a][b] at out[a*s+b]) for this workgroup.  `lds` must hold

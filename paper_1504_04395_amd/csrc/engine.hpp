@@ -21,6 +21,8 @@
 
 namespace skr {
 
+constexpr int kScalar = 64;   // one wavefront for the one-workgroup coefficient kernels
+
 struct HipError {
     hipError_t e;
     const char* what;
@@ -107,22 +109,30 @@ void env_layout(Env<T>& e, int n, int s) {
 }
 
 // ------------------------------------------------------------------ launch helpers
-template <class T, int J, class Epi>
+template <class T, int J, class Epi, int J16 = (J == 1 ? 1 : 2)>
 void spmm_j(Env<T>& e, const Operand<T>& op, const Layout& ly, const T* X, T* Y, Epi epi, const Ctl* ctl) {
     if (op.sell) {
         int nchunks = (e.n + op.sl.C - 1) / op.sl.C;
         int cpb = (nchunks + e.nb - 1) / e.nb;
         k_spmm_sell<T, J, Epi><<<e.nb, kBlock, 0, e.st>>>(ctl, op.sl, ly, cpb, X, Y, epi);
     } else {
-        k_spmm_csr<T, J, Epi><<<e.nb, kBlock, 0, e.st>>>(ctl, op.csr, ly, e.rpc, X, Y, epi);
+        // CSR kernel: 16 lanes per row whatever s is (its lane layout is the DPP row)
+        const Layout l16{ly.s, 16, 4};
+        const int step = 32;                           // RP * 16 rows per workgroup pass (upper bound)
+        const int per_xcd = ((e.n + 7) / 8 + step - 1) / step * step;
+        k_spmm_csr<T, J16, Epi><<<e.nb, kBlock, 0, e.st>>>(ctl, op.csr, l16, per_xcd, X, Y, epi);
     }
     SKR_LAUNCHED();
 }
 template <class T, class Epi>
 void spmm(Env<T>& e, const Operand<T>& op, const Layout& ly, const T* X, T* Y, Epi epi, const Ctl* ctl) {
-    int J = (ly.s + ly.L - 1) / ly.L;
-    if (J == 1) spmm_j<T, 1>(e, op, ly, X, Y, epi, ctl);
-    else spmm_j<T, 2>(e, op, ly, X, Y, epi, ctl);
+    // J of the SELL kernel follows ly; the CSR kernel always uses 16 lanes, J16 = ceil(s/16)
+    const int J = (ly.s + ly.L - 1) / ly.L;
+    const bool j16 = ly.s > 16;
+    if (J == 1 && !j16) spmm_j<T, 1, Epi, 1>(e, op, ly, X, Y, epi, ctl);
+    else if (J == 1) spmm_j<T, 1, Epi, 2>(e, op, ly, X, Y, epi, ctl);
+    else if (!j16) spmm_j<T, 2, Epi, 1>(e, op, ly, X, Y, epi, ctl);
+    else spmm_j<T, 2, Epi, 2>(e, op, ly, X, Y, epi, ctl);
 }
 template <class T>
 Layout tile_layout(const Env<T>& e) { return Layout{e.s, 16, 4}; }
@@ -134,39 +144,44 @@ void reduce2(Env<T>& e, int E, int cond_slot = -1) {
     SKR_LAUNCHED();
 }
 
+// Dynamic LDS of a tile kernel: nmat s x s matrices and ntile row tiles of
+// RowPasses * 16 rows, in complex FP64 slots (real kernels use half), and at
+// least the Gram reduction buffer.
 inline size_t mat_lds(int s, int nmat, int ntile) {
     size_t J = (s + 15) / 16;
-    size_t need = (size_t)nmat * s * s + (size_t)ntile * 16 * s;
+    size_t rp = s <= 16 ? 2 : 1;   // RowPasses tiles measured in complex FP64 slots
+    size_t need = (size_t)nmat * s * s + (size_t)ntile * rp * 16 * s;
     size_t gram = (16 * J) * (16 * J);
     return (need > gram ? need : gram) * sizeof(c64);
 }
 
 // CholeskyQR2 (+ shifted first pass) of Z into Q; the Gram Z^H Z partials must
-// already be in e.part.  Final factor in mats (slot 0: M_S / M_SINV, slot 1:
-// M_T / M_TINV).  mode/Other: Gram fused into the final pass (TRI_* flags).
+// already be in e.part.  R factor in mats (slot 0: M_S, slot 1: M_T).
+// mode/Other: Gram fused into the final pass (TRI_* flags).
 template <class T, int J>
 void cholqr(Env<T>& e, int slot, const T* Z, T* Q, int mode, const T* Other) {
     const int s = e.s, ss = s * s;
-    const int base = slot == 0 ? M_S1 : M_T1;
-    size_t lds6 = 6 * (size_t)ss * sizeof(c64);
-    size_t ldsT = mat_lds(s, 1, 1);
+    size_t lds4 = 4 * (size_t)ss * sizeof(c64);
+    size_t ldsT = mat_lds(s, 3, 1);
     reduce2(e, ss);
-    k_qr_chol<<<1, kBlock, lds6, e.st>>>(e.ctl, slot, 1, e.n, s, e.part2, e.p2, e.mats);
+    k_qr_chol<<<1, kScalar, lds4, e.st>>>(e.ctl, slot, 1, e.n, s, e.part2, e.p2, e.mats);
     SKR_LAUNCHED();
-    k_bl_tri<T, J><<<e.nb, kBlock, ldsT, e.st>>>(e.ctl, -1, e.tl, TRI_G_OUT_OUT, e.mats, base + 1, Z, nullptr,
+    // Gram of Q1 = Z S1^{-1}
+    k_bl_tri<T, J><<<e.nb, kBlock, ldsT, e.st>>>(e.ctl, slot, 0, 1, 0, e.tl, TRI_G_OUT_OUT, e.mats, Z, nullptr,
                                                  nullptr, e.part);
     SKR_LAUNCHED();
     reduce2(e, ss);
-    k_qr_chol<<<1, kBlock, lds6, e.st>>>(e.ctl, slot, 2, e.n, s, e.part2, e.p2, e.mats);
+    k_qr_chol<<<1, kScalar, lds4, e.st>>>(e.ctl, slot, 2, e.n, s, e.part2, e.p2, e.mats);
     SKR_LAUNCHED();
-    // shifted case only: one more pass with Q2 = Z (S2 S1)^{-1}
-    k_bl_tri<T, J><<<e.nb, kBlock, ldsT, e.st>>>(e.ctl, slot, e.tl, TRI_G_OUT_OUT, e.mats, base + 3, Z, nullptr,
+    // shifted case only: Gram of Q2 = Z S1^{-1} S2^{-1}
+    k_bl_tri<T, J><<<e.nb, kBlock, ldsT, e.st>>>(e.ctl, slot, 1, 2, 0, e.tl, TRI_G_OUT_OUT, e.mats, Z, nullptr,
                                                  nullptr, e.part);
     SKR_LAUNCHED();
     reduce2(e, ss, slot);
-    k_qr_chol<<<1, kBlock, lds6, e.st>>>(e.ctl, slot, 3, e.n, s, e.part2, e.p2, e.mats);
+    k_qr_chol<<<1, kScalar, lds4, e.st>>>(e.ctl, slot, 3, e.n, s, e.part2, e.p2, e.mats);
     SKR_LAUNCHED();
-    k_bl_tri<T, J><<<e.nb, kBlock, ldsT, e.st>>>(e.ctl, -1, e.tl, mode | TRI_WRITE, e.mats, base + 5, Z, Q, Other,
+    // Q = Z S1^{-1} S2^{-1} [S3^{-1}]
+    k_bl_tri<T, J><<<e.nb, kBlock, ldsT, e.st>>>(e.ctl, slot, 0, 2, 1, e.tl, mode | TRI_WRITE, e.mats, Z, Q, Other,
                                                  e.part);
     SKR_LAUNCHED();
 }
@@ -197,16 +212,16 @@ Method<T> make_gl_bicg(Env<T>& e, Arena& ar, T* rhs, T* x) {
         k_copy<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, rhs, Ph, nullptr, nullptr);
         k_fill0<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, x, nullptr, nullptr, nullptr);
         k_flat_nrm_dot<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, R, Rh, e.part);
-        k_s_rho0<<<1, kBlock, 0, e.st>>>(e.part, e.nb, 1, 2, e.sc);
-        k_init_ctl2<<<1, kBlock, 0, e.st>>>(e.ctl, e.hist, e.part, e.nb);
+        k_s_rho0<<<1, kScalar, 0, e.st>>>(e.part, e.nb, 1, 2, e.sc);
+        k_init_ctl2<<<1, kScalar, 0, e.st>>>(e.ctl, e.hist, e.part, e.nb);
         SKR_LAUNCHED();
     };
     m.iter = [=, &e]() {
         spmm(e, e.A, e.ly, P, Q, EpiTrace<T>{Ph, e.part}, e.ctl);
         spmm(e, e.AH, e.ly, Ph, Zh, EpiNone{}, e.ctl);
-        k_s_alpha<<<1, kBlock, 0, e.st>>>(e.ctl, e.part, e.nb, e.sc);
+        k_s_alpha<<<1, kScalar, 0, e.st>>>(e.ctl, e.part, e.nb, e.sc);
         k_glbicg_upd<T><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.fl, e.sc, x, R, Rh, P, Q, Zh, e.part);
-        k_s_beta<<<1, kBlock, 0, e.st>>>(e.ctl, e.hist, e.part, e.nb, e.sc);
+        k_s_beta<<<1, kScalar, 0, e.st>>>(e.ctl, e.hist, e.part, e.nb, e.sc);
         k_glbicg_dir<T><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.fl, e.sc, R, Rh, P, Ph);
         SKR_LAUNCHED();
     };
@@ -230,16 +245,16 @@ Method<T> make_egl_bicg(Env<T>& e, Arena& ar, T* rhs, T* x) {
         Flat fv{(size_t)e.n, (((size_t)e.n + e.nb - 1) / e.nb + kBlock - 1) / kBlock * kBlock};
         k_copy<T><<<e.nb, kBlock, 0, e.st>>>(fv, rh, ph, nullptr, nullptr);
         k_egl_init_red2<T><<<e.nb, kBlock, 0, e.st>>>(e.ly, e.n, e.rpc, R, rh, e.part);
-        k_s_rho0<<<1, kBlock, 0, e.st>>>(e.part, e.nb, 1, 2, e.sc);
-        k_init_ctl2<<<1, kBlock, 0, e.st>>>(e.ctl, e.hist, e.part, e.nb);
+        k_s_rho0<<<1, kScalar, 0, e.st>>>(e.part, e.nb, 1, 2, e.sc);
+        k_init_ctl2<<<1, kScalar, 0, e.st>>>(e.ctl, e.hist, e.part, e.nb);
         SKR_LAUNCHED();
     };
     m.iter = [=, &e]() {
         spmm(e, e.A, e.ly, P, Q, EpiVecSum<T>{ph, e.part}, e.ctl);
         spmm(e, e.AH, e.lyv, ph, zh, EpiNone{}, e.ctl);
-        k_s_alpha<<<1, kBlock, 0, e.st>>>(e.ctl, e.part, e.nb, e.sc);
+        k_s_alpha<<<1, kScalar, 0, e.st>>>(e.ctl, e.part, e.nb, e.sc);
         k_eglbicg_upd<T><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.ly, e.n, e.rpc, e.sc, x, R, rh, P, Q, zh, e.part);
-        k_s_beta<<<1, kBlock, 0, e.st>>>(e.ctl, e.hist, e.part, e.nb, e.sc);
+        k_s_beta<<<1, kScalar, 0, e.st>>>(e.ctl, e.hist, e.part, e.nb, e.sc);
         k_eglbicg_dir<T><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.ly, e.n, e.rpc, e.sc, R, rh, P, ph);
         SKR_LAUNCHED();
     };
@@ -264,20 +279,20 @@ Method<T> make_gl_qmr(Env<T>& e, Arena& ar, T* rhs, T* x) {
         k_fill0<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, x, D, S, P);
         k_fill0<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, Qd, nullptr, nullptr, nullptr);
         k_flat_nrm_dot<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, R, nullptr, e.part);
-        k_init_ctl2<<<1, kBlock, 0, e.st>>>(e.ctl, e.hist, e.part, e.nb);
+        k_init_ctl2<<<1, kScalar, 0, e.st>>>(e.ctl, e.hist, e.part, e.nb);
         k_gl_init_red3<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, V, W, e.part);
-        k_qmr_s0<<<1, kBlock, 0, e.st>>>(e.ctl, e.part, e.nb, e.sc, 1.0);
+        k_qmr_s0<<<1, kScalar, 0, e.st>>>(e.ctl, e.part, e.nb, e.sc, 1.0);
         k_glqmr_step<T><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.fl, e.sc, 0, x, R, D, S, P, Pt, V, W, Qd, e.part);
         SKR_LAUNCHED();
     };
     m.iter = [=, &e]() {
         spmm(e, e.A, e.ly, P, Pt, EpiTrace<T>{Qd, e.part}, e.ctl);
         spmm(e, e.AH, e.ly, Qd, Zh, EpiNone{}, e.ctl);
-        k_qmr_s1<<<1, kBlock, 0, e.st>>>(e.ctl, e.part, e.nb, e.sc);
+        k_qmr_s1<<<1, kScalar, 0, e.st>>>(e.ctl, e.part, e.nb, e.sc);
         k_glqmr_lanczos<T><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.fl, e.sc, V, W, Pt, Zh, e.part);
-        k_qmr_s2<<<1, kBlock, 0, e.st>>>(e.ctl, e.part, e.nb, e.sc, 1.0);
+        k_qmr_s2<<<1, kScalar, 0, e.st>>>(e.ctl, e.part, e.nb, e.sc, 1.0);
         k_glqmr_step<T><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.fl, e.sc, 1, x, R, D, S, P, Pt, V, W, Qd, e.part);
-        k_qmr_s3<<<1, kBlock, 0, e.st>>>(e.ctl, e.hist, e.part, e.nb, e.sc);
+        k_qmr_s3<<<1, kScalar, 0, e.st>>>(e.ctl, e.hist, e.part, e.nb, e.sc);
         SKR_LAUNCHED();
     };
     return m;
@@ -304,9 +319,9 @@ Method<T> make_egl_qmr(Env<T>& e, Arena& ar, T* rhs, T* x) {
         Flat fv{(size_t)e.n, (((size_t)e.n + e.nb - 1) / e.nb + kBlock - 1) / kBlock * kBlock};
         k_fill0<T><<<e.nb, kBlock, 0, e.st>>>(fv, qd, nullptr, nullptr, nullptr);
         k_flat_nrm_dot<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, R, nullptr, e.part);
-        k_init_ctl2<<<1, kBlock, 0, e.st>>>(e.ctl, e.hist, e.part, e.nb);
+        k_init_ctl2<<<1, kScalar, 0, e.st>>>(e.ctl, e.hist, e.part, e.nb);
         k_egl_init_red<T><<<e.nb, kBlock, 0, e.st>>>(e.ly, e.n, e.rpc, V, w, e.part);
-        k_qmr_s0<<<1, kBlock, 0, e.st>>>(e.ctl, e.part, e.nb, e.sc, xs);
+        k_qmr_s0<<<1, kScalar, 0, e.st>>>(e.ctl, e.part, e.nb, e.sc, xs);
         k_eglqmr_step<T><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.ly, e.n, e.rpc, e.sc, 0, x, R, D, S, P, Pt, V, w, qd,
                                                      e.part);
         SKR_LAUNCHED();
@@ -314,12 +329,12 @@ Method<T> make_egl_qmr(Env<T>& e, Arena& ar, T* rhs, T* x) {
     m.iter = [=, &e]() {
         spmm(e, e.A, e.ly, P, Pt, EpiVecSum<T>{qd, e.part}, e.ctl);
         spmm(e, e.AH, e.lyv, qd, zh, EpiNone{}, e.ctl);
-        k_qmr_s1<<<1, kBlock, 0, e.st>>>(e.ctl, e.part, e.nb, e.sc);
+        k_qmr_s1<<<1, kScalar, 0, e.st>>>(e.ctl, e.part, e.nb, e.sc);
         k_eglqmr_lanczos<T><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.ly, e.n, e.rpc, e.sc, V, w, Pt, zh, e.part);
-        k_qmr_s2<<<1, kBlock, 0, e.st>>>(e.ctl, e.part, e.nb, e.sc, xs);
+        k_qmr_s2<<<1, kScalar, 0, e.st>>>(e.ctl, e.part, e.nb, e.sc, xs);
         k_eglqmr_step<T><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.ly, e.n, e.rpc, e.sc, 1, x, R, D, S, P, Pt, V, w, qd,
                                                      e.part);
-        k_qmr_s3<<<1, kBlock, 0, e.st>>>(e.ctl, e.hist, e.part, e.nb, e.sc);
+        k_qmr_s3<<<1, kScalar, 0, e.st>>>(e.ctl, e.hist, e.part, e.nb, e.sc);
         SKR_LAUNCHED();
     };
     return m;
@@ -339,18 +354,18 @@ Method<T> make_gl_bicgstab(Env<T>& e, Arena& ar, T* rhs, T* x) {
         k_copy<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, rhs, R, Rt, P);
         k_fill0<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, x, nullptr, nullptr, nullptr);
         k_flat_nrm_dot<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, R, Rt, e.part);
-        k_s_rho0<<<1, kBlock, 0, e.st>>>(e.part, e.nb, 1, 2, e.sc);
-        k_init_ctl2<<<1, kBlock, 0, e.st>>>(e.ctl, e.hist, e.part, e.nb);
+        k_s_rho0<<<1, kScalar, 0, e.st>>>(e.part, e.nb, 1, 2, e.sc);
+        k_init_ctl2<<<1, kScalar, 0, e.st>>>(e.ctl, e.hist, e.part, e.nb);
         SKR_LAUNCHED();
     };
     m.iter = [=, &e]() {
         spmm(e, e.A, e.ly, P, V, EpiTrace<T>{Rt, e.part}, e.ctl);
-        k_s_alpha<<<1, kBlock, 0, e.st>>>(e.ctl, e.part, e.nb, e.sc);
+        k_s_alpha<<<1, kScalar, 0, e.st>>>(e.ctl, e.part, e.nb, e.sc);
         k_stab_s<T><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.fl, e.sc, R, V, S);
         spmm(e, e.A, e.ly, S, Tm, EpiTraceOmega<T>{S, e.part}, e.ctl);
-        k_s_omega<<<1, kBlock, 0, e.st>>>(e.ctl, e.part, e.nb, e.sc);
+        k_s_omega<<<1, kScalar, 0, e.st>>>(e.ctl, e.part, e.nb, e.sc);
         k_stab_upd<T><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.fl, e.sc, x, R, Rt, P, S, Tm, e.part);
-        k_s_stab_beta<<<1, kBlock, 0, e.st>>>(e.ctl, e.hist, e.part, e.nb, e.sc);
+        k_s_stab_beta<<<1, kScalar, 0, e.st>>>(e.ctl, e.hist, e.part, e.nb, e.sc);
         k_stab_dir<T><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.fl, e.sc, R, V, P);
         SKR_LAUNCHED();
     };
@@ -377,7 +392,7 @@ Method<T> make_bl_bicg_rq(Env<T>& e, Arena& ar, T* rhs, T* x) {
         SKR_LAUNCHED();
         cholqr<T, J>(e, 0, rhs, Q, TRI_G_OUT_OUT, nullptr);   // Q0, C0 = S, M = Q0^H Q0
         reduce2(e, ss);
-        k_bl_init<<<1, kBlock, 6 * (size_t)ss * sizeof(c64), e.st>>>(e.ctl, e.hist, s, 1, e.part2, e.p2, M_M,
+        k_bl_init<<<1, kScalar, 4 * (size_t)ss * sizeof(c64), e.st>>>(e.ctl, e.hist, s, 1, e.part2, e.p2, M_M,
                                                                       e.mats);
         k_copy<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, Q, Qh, V, Vh);
         SKR_LAUNCHED();
@@ -386,7 +401,7 @@ Method<T> make_bl_bicg_rq(Env<T>& e, Arena& ar, T* rhs, T* x) {
         spmm_j<T, J>(e, e.A, lt, V, W, EpiGram<T, J>{Vh, e.part}, e.ctl);           // W = A V, G = V^^H W
         spmm_j<T, J>(e, e.AH, lt, Vh, Wh, EpiNone{}, e.ctl);                      // W^ = A^H V^
         reduce2(e, ss);
-        k_blrq_alpha<<<1, kBlock, 6 * (size_t)ss * sizeof(c64), e.st>>>(e.ctl, s, e.part2, e.p2, e.mats, e.sc);
+        k_blrq_alpha<<<1, kScalar, 4 * (size_t)ss * sizeof(c64), e.st>>>(e.ctl, s, e.part2, e.p2, e.mats, e.sc);
         k_blrq_updz<T, J><<<e.nb, kBlock, mat_lds(s, 2, 2), e.st>>>(e.ctl, e.tl, e.mats, x, V, Q, W, Z, e.part);
         SKR_LAUNCHED();
         cholqr<T, J>(e, 0, Z, Q, 0, nullptr);                                     // Q' S = Q - W alpha
@@ -395,7 +410,7 @@ Method<T> make_bl_bicg_rq(Env<T>& e, Arena& ar, T* rhs, T* x) {
         SKR_LAUNCHED();
         cholqr<T, J>(e, 1, Zh, Qh, TRI_G_OUT_OTHER, Q);                           // Q^' S^, M' = Q^'^H Q'
         reduce2(e, ss);
-        k_blrq_beta<<<1, kBlock, 6 * (size_t)ss * sizeof(c64), e.st>>>(e.ctl, e.hist, s, e.part2, e.p2, e.mats);
+        k_blrq_beta<<<1, kScalar, 4 * (size_t)ss * sizeof(c64), e.st>>>(e.ctl, e.hist, s, e.part2, e.p2, e.mats);
         k_bl_axpm<T, J, false><<<e.nb, kBlock, mat_lds(s, 1, 1), e.st>>>(e.ctl, e.tl, e.mats, M_BETA, e.sc, 0,
                                                                         Q, V, nullptr, V, e.part);
         k_bl_axpm<T, J, false><<<e.nb, kBlock, mat_lds(s, 1, 1), e.st>>>(e.ctl, e.tl, e.mats, M_BETAH, e.sc, 0,
@@ -425,7 +440,7 @@ Method<T> make_bl_bicgstab_rq(Env<T>& e, Arena& ar, T* rhs, T* x) {
         SKR_LAUNCHED();
         cholqr<T, J>(e, 0, rhs, Q, TRI_G_OTHER_OUT, Rt);                         // Q0, N = R~^H Q0
         reduce2(e, ss);
-        k_bl_init<<<1, kBlock, 6 * (size_t)ss * sizeof(c64), e.st>>>(e.ctl, e.hist, s, 0, e.part2, e.p2, M_N,
+        k_bl_init<<<1, kScalar, 4 * (size_t)ss * sizeof(c64), e.st>>>(e.ctl, e.hist, s, 0, e.part2, e.p2, M_N,
                                                                       e.mats);
         k_copy<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, Q, U, nullptr, nullptr);
         SKR_LAUNCHED();
@@ -433,19 +448,19 @@ Method<T> make_bl_bicgstab_rq(Env<T>& e, Arena& ar, T* rhs, T* x) {
     m.iter = [=, &e]() {
         spmm_j<T, J>(e, e.A, lt, U, W, EpiGram<T, J>{Rt, e.part}, e.ctl);           // W = A U, G = R~^H W
         reduce2(e, ss);
-        k_blst_a<<<1, kBlock, 6 * (size_t)ss * sizeof(c64), e.st>>>(e.ctl, s, e.part2, e.p2, e.mats, e.sc);
+        k_blst_a<<<1, kScalar, 4 * (size_t)ss * sizeof(c64), e.st>>>(e.ctl, s, e.part2, e.p2, e.mats, e.sc);
         k_bl_axpm<T, J, false><<<e.nb, kBlock, mat_lds(s, 1, 1), e.st>>>(e.ctl, e.tl, e.mats, M_TMP, e.sc, 0,
                                                                         Q, W, nullptr, St, e.part);  // S~ = Q - W a
         SKR_LAUNCHED();
         spmm_j<T, J>(e, e.A, lt, St, Tt, EpiGramOmega<T, J>{St, e.part}, e.ctl);    // T~ = A S~
         reduce2(e, 2 * ss);
-        k_blst_omega<<<1, kBlock, 6 * (size_t)ss * sizeof(c64), e.st>>>(e.ctl, s, e.part2, e.p2, e.mats, e.sc);
+        k_blst_omega<<<1, kScalar, 4 * (size_t)ss * sizeof(c64), e.st>>>(e.ctl, s, e.part2, e.p2, e.mats, e.sc);
         k_blst_upd<T, J><<<e.nb, kBlock, mat_lds(s, 2, 2), e.st>>>(e.ctl, e.tl, e.mats, e.sc, x, U, St, Tt, Z,
                                                                   e.part);
         SKR_LAUNCHED();
         cholqr<T, J>(e, 0, Z, Q, TRI_G_OTHER_OUT, Rt);                            // Q' Sigma = Z, N' = R~^H Q'
         reduce2(e, ss);
-        k_blst_b<<<1, kBlock, 6 * (size_t)ss * sizeof(c64), e.st>>>(e.ctl, e.hist, s, e.part2, e.p2, e.mats, e.sc);
+        k_blst_b<<<1, kScalar, 4 * (size_t)ss * sizeof(c64), e.st>>>(e.ctl, e.hist, s, e.part2, e.p2, e.mats, e.sc);
         k_bl_axpm<T, J, false><<<e.nb, kBlock, mat_lds(s, 1, 1), e.st>>>(e.ctl, e.tl, e.mats, M_B, e.sc,
                                                                         SC_GAMMA, Q, U, W, U, e.part);
         SKR_LAUNCHED();

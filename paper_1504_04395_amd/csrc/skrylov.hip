@@ -69,26 +69,26 @@ template <class T, class Td, int J>
 __global__ __launch_bounds__(kBlock) void k_xupd(Tile16 tl, const c64* __restrict__ mats, int mslot,
                                                  T* __restrict__ X, const Td* __restrict__ D, int zero_x) {
     extern __shared__ c64 dyn[];
+    using VV = Val<T>;
     const int s = tl.s;
-    c64* M = dyn;
-    c64* tile = dyn + s * s;
+    VV* M = reinterpret_cast<VV*>(dyn);
     if (mslot >= 0) lds_load_mat(M, mats + (size_t)mslot * s * s, s);
+    __syncthreads();
+    Coef<T, J> cf;
+    if (mslot >= 0) cf.load(M, s, threadIdx.x & 15);
     SKR_TILE_LOOP(tl) {
         const int i = base_ + grp;
         const bool valid = i < r1_;
-        c64 d[J], x[J];
+        VV d[J], x[J];
         load_row<Td, J>(D, i, valid, lane, s, d);
         if (zero_x) {
 #pragma unroll
-            for (int j = 0; j < J; ++j) x[j] = {0.0, 0.0};
+            for (int j = 0; j < J; ++j) x[j] = vzero<VV>();
         } else {
             load_row<T, J>(X, i, valid, lane, s, x);
         }
         if (mslot >= 0) {
-            __syncthreads();
-            put_tile<J>(tile, grp, lane, s, d);
-            __syncthreads();
-            tile_times<J>(tile, M, grp, lane, s, x);
+            cf.apply(d, lane, x);
         } else {
 #pragma unroll
             for (int j = 0; j < J; ++j) x[j] = x[j] + d[j];
@@ -489,7 +489,7 @@ template <class T>
 void true_residual(skr_context* c, Env<T>& e, const T* B, const T* X, T* tmp, double* rn2, double* bn2) {
     spmm(e, e.A, e.ly, X, tmp, EpiNone{}, (const Ctl*)nullptr);
     k_resid<T, T><<<e.nb, kBlock, 0, e.st>>>(e.fl, B, tmp, (T*)nullptr, (T*)nullptr, e.part);
-    k_sum2<<<1, kBlock, 0, e.st>>>(e.part, e.nb, e.sc + 100);
+    k_sum2<<<1, kScalar, 0, e.st>>>(e.part, e.nb, e.sc + 100);
     SKR_LAUNCHED();
     SKR_HIP(hipMemcpyAsync(c->hsum, e.sc + 100, 2 * sizeof(c64), hipMemcpyDeviceToHost, e.st));
     SKR_HIP(hipStreamSynchronize(e.st));
@@ -509,7 +509,7 @@ bool preprocess(skr_context* c, Env<T>& e, T* rhs) {
     k_bl_gram<T, J><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.tl, rhs, rhs, e.part);
     SKR_LAUNCHED();
     cholqr<T, J>(e, 0, rhs, rhs, 0, nullptr);
-    k_copy_mat<<<1, kBlock, 0, e.st>>>(e.mats, e.s, M_S, M_RB);
+    k_copy_mat<<<1, kScalar, 0, e.st>>>(e.mats, e.s, M_S, M_RB);
     SKR_LAUNCHED();
     SKR_HIP(hipMemcpyAsync(c->hout, e.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, e.st));
     SKR_HIP(hipStreamSynchronize(e.st));
@@ -637,7 +637,7 @@ int solve_mixed(skr_context* c, skr_matrix* M, int s, const T* B, T* X, bool x0z
     for (;;) {
         spmm(e, e.A, e.ly, X, tmp, EpiNone{}, (const Ctl*)nullptr);
         k_resid<T, L><<<e.nb, kBlock, 0, e.st>>>(e.fl, B, tmp, (T*)nullptr, r32, e.part);
-        k_sum2<<<1, kBlock, 0, e.st>>>(e.part, e.nb, e.sc + 100);
+        k_sum2<<<1, kScalar, 0, e.st>>>(e.part, e.nb, e.sc + 100);
         SKR_LAUNCHED();
         SKR_HIP(hipMemcpyAsync(c->hsum, e.sc + 100, 2 * sizeof(c64), hipMemcpyDeviceToHost, e.st));
         SKR_HIP(hipStreamSynchronize(e.st));
@@ -705,7 +705,7 @@ bool finite_block(skr_context* c, const void* P, int n, int w) {
     ar.base = c->arena;
     take_common(e, ar, 1);
     k_flat_nrm_dot<double><<<e.nb, kBlock, 0, e.st>>>(e.fl, (const double*)P, nullptr, e.part);
-    k_sum2<<<1, kBlock, 0, e.st>>>(e.part, e.nb, e.sc + 100);
+    k_sum2<<<1, kScalar, 0, e.st>>>(e.part, e.nb, e.sc + 100);
     SKR_LAUNCHED();
     SKR_HIP(hipMemcpyAsync(c->hsum, e.sc + 100, 2 * sizeof(c64), hipMemcpyDeviceToHost, e.st));
     SKR_HIP(hipStreamSynchronize(e.st));
@@ -881,6 +881,15 @@ int skr_matrix_create(skr_context* c, int64_t n64, int64_t nnz64, const int64_t*
         SKR_HIP(hipMalloc(&M->vaH, std::max<size_t>(1, es * nnz)));
         SKR_HIP(hipMemcpy(M->rp, rp.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice));
         SKR_HIP(hipMemcpy(M->rpH, rpH.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice));
+        if (nnz == 0) {
+            // the sparse kernels read a clamped entry even for empty rows: keep one
+            // valid (column 0, value 0) slot
+            SKR_HIP(hipMemset(M->ci, 0, sizeof(int)));
+            SKR_HIP(hipMemset(M->ciH, 0, sizeof(int)));
+            SKR_HIP(hipMemset(M->perm, 0, sizeof(int)));
+            SKR_HIP(hipMemset(M->va, 0, es));
+            SKR_HIP(hipMemset(M->vaH, 0, es));
+        }
         if (nnz) {
             SKR_HIP(hipMemcpy(M->ci, ci.data(), sizeof(int) * nnz, hipMemcpyHostToDevice));
             SKR_HIP(hipMemcpy(M->ciH, ciH.data(), sizeof(int) * nnz, hipMemcpyHostToDevice));

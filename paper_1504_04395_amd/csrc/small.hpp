@@ -111,71 +111,60 @@ __device__ inline int sm_lu(c64* A, int* piv, int s, int* flag /* shared */) {
 }
 
 // B := G^{-1} B for B s x m (row-major, leading dimension m), G = P^T L U.
+// Columns of B are independent: thread j solves column j (no barriers inside).
 __device__ inline void sm_lu_solve(const c64* LU, const int* piv, c64* B, int s, int m) {
-    for (int k = 0; k < s; ++k) {
-        int p = piv[k];
-        if (p != k) {
-            for (int j = threadIdx.x; j < m; j += blockDim.x) {
+    for (int j = threadIdx.x; j < m; j += blockDim.x) {
+        for (int k = 0; k < s; ++k) {
+            int p = piv[k];
+            if (p != k) {
                 c64 t = B[k * m + j];
                 B[k * m + j] = B[p * m + j];
                 B[p * m + j] = t;
             }
         }
-        __syncthreads();
-    }
-    for (int k = 0; k < s; ++k) {  // unit lower
-        for (int e = threadIdx.x; e < (s - k - 1) * m; e += blockDim.x) {
-            int i = k + 1 + e / m, j = e % m;
-            B[i * m + j] = B[i * m + j] - LU[i * s + k] * B[k * m + j];
+        for (int k = 0; k < s; ++k) {  // unit lower
+            const c64 bk = B[k * m + j];
+            for (int i = k + 1; i < s; ++i) B[i * m + j] = B[i * m + j] - LU[i * s + k] * bk;
         }
-        __syncthreads();
-    }
-    for (int k = s - 1; k >= 0; --k) {  // upper
-        for (int j = threadIdx.x; j < m; j += blockDim.x) B[k * m + j] = cdiv(B[k * m + j], LU[k * s + k]);
-        __syncthreads();
-        for (int e = threadIdx.x; e < k * m; e += blockDim.x) {
-            int i = e / m, j = e % m;
-            B[i * m + j] = B[i * m + j] - LU[i * s + k] * B[k * m + j];
+        for (int k = s - 1; k >= 0; --k) {  // upper
+            const c64 bk = cdiv(B[k * m + j], LU[k * s + k]);
+            B[k * m + j] = bk;
+            for (int i = 0; i < k; ++i) B[i * m + j] = B[i * m + j] - LU[i * s + k] * bk;
         }
-        __syncthreads();
     }
+    __syncthreads();
 }
 
-// B := G^{-H} B, with G = P^T L U, i.e. solve U^H L^H P X = B.
+// B := G^{-H} B, with G = P^T L U, i.e. solve U^H L^H P X = B (column-parallel).
 __device__ inline void sm_lu_solve_h(const c64* LU, const int* piv, c64* B, int s, int m) {
-    for (int k = 0; k < s; ++k) {  // U^H (lower, diagonal conj(u_kk))
-        for (int j = threadIdx.x; j < m; j += blockDim.x) B[k * m + j] = cdiv(B[k * m + j], conj_(LU[k * s + k]));
-        __syncthreads();
-        for (int e = threadIdx.x; e < (s - k - 1) * m; e += blockDim.x) {
-            int i = k + 1 + e / m, j = e % m;
-            B[i * m + j] = B[i * m + j] - conj_(LU[k * s + i]) * B[k * m + j];
+    for (int j = threadIdx.x; j < m; j += blockDim.x) {
+        for (int k = 0; k < s; ++k) {  // U^H (lower, diagonal conj(u_kk))
+            const c64 bk = cdiv(B[k * m + j], conj_(LU[k * s + k]));
+            B[k * m + j] = bk;
+            for (int i = k + 1; i < s; ++i) B[i * m + j] = B[i * m + j] - conj_(LU[k * s + i]) * bk;
         }
-        __syncthreads();
-    }
-    for (int k = s - 1; k >= 0; --k) {  // L^H (unit upper)
-        for (int e = threadIdx.x; e < k * m; e += blockDim.x) {
-            int i = e / m, j = e % m;
-            B[i * m + j] = B[i * m + j] - conj_(LU[k * s + i]) * B[k * m + j];
+        for (int k = s - 1; k >= 0; --k) {  // L^H (unit upper)
+            const c64 bk = B[k * m + j];
+            for (int i = 0; i < k; ++i) B[i * m + j] = B[i * m + j] - conj_(LU[k * s + i]) * bk;
         }
-        __syncthreads();
-    }
-    for (int k = s - 1; k >= 0; --k) {  // X = P^T W
-        int p = piv[k];
-        if (p != k) {
-            for (int j = threadIdx.x; j < m; j += blockDim.x) {
+        for (int k = s - 1; k >= 0; --k) {  // X = P^T W
+            int p = piv[k];
+            if (p != k) {
                 c64 t = B[k * m + j];
                 B[k * m + j] = B[p * m + j];
                 B[p * m + j] = t;
             }
         }
-        __syncthreads();
     }
+    __syncthreads();
 }
 
 // In-place upper Cholesky factor G = S^H S of a Hermitian matrix (upper
 // triangle of G is used; the strict lower triangle is set to 0).  `shift` is
 // added to the diagonal first.  Returns 1 on success, 0 if a pivot is not
-// safely positive (d <= 1e-14 * original diagonal, or not finite).
+// safely positive (d <= 1e-12 * largest original diagonal entry, i.e. a
+// condition number beyond ~1e6, or not finite): past that point a second
+// CholeskyQR pass no longer restores orthogonality to rounding level.
 __device__ inline int sm_cholesky(c64* G, int s, double shift, int* flag /* shared */) {
     __shared__ double diag0[kMaxS];
     for (int i = threadIdx.x; i < s; i += blockDim.x) {
@@ -185,9 +174,11 @@ __device__ inline int sm_cholesky(c64* G, int s, double shift, int* flag /* shar
     }
     if (threadIdx.x == 0) *flag = 1;
     __syncthreads();
+    double dmax = 0.0;
+    for (int i = 0; i < s; ++i) dmax = fmax(dmax, diag0[i]);
     for (int k = 0; k < s; ++k) {
         double d = G[k * s + k].x;
-        bool bad = !(d > 1e-14 * diag0[k]) || !isfinite(d) || !(diag0[k] > 0.0);
+        bool bad = !(d > 1e-12 * dmax) || !isfinite(d) || !(diag0[k] > 0.0);
         if (bad) {
             if (threadIdx.x == 0) *flag = 0;
             __syncthreads();

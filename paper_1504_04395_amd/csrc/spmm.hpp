@@ -18,6 +18,8 @@
 
 #include "common.hpp"
 
+#include <type_traits>
+
 namespace skr {
 
 template <class T>
@@ -176,46 +178,108 @@ __device__ inline void epi_finish(E& e, typename E::St& st, int b, int s) {
 }
 
 // ------------------------------------------------------------------ kernels
-// Workgroup b (after the XCD remap) owns rows [chunk*rows_per_chunk, ...).
+// 32-bit broadcast of lane N of each 16-lane row (DPP row_newbcast).
+template <int N>
+__device__ inline int rbc32(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x150 + N, 0xF, 0xF, false); }
+template <int N>
+__device__ inline double rbc64(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), 0x150 + N, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x150 + N, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, (long long)(unsigned)lo | ((long long)hi << 32));
+}
+template <int N>
+__device__ inline float rbc64(float v) { return __builtin_bit_cast(float, rbc32<N>(__builtin_bit_cast(int, v))); }
+template <int N>
+__device__ inline c64 rbc64(c64 v) { return {rbc64<N>(v.x), rbc64<N>(v.y)}; }
+template <int N>
+__device__ inline c32 rbc64(c32 v) { return {rbc64<N>(v.x), rbc64<N>(v.y)}; }
+
+template <int A, int END, class F>
+__device__ inline void sfor(F&& f) {
+    if constexpr (A < END) {
+        f(std::integral_constant<int, A>{});
+        sfor<A + 1, END>(f);
+    }
+}
+
+// Row mapping: XCD x (= workgroup index mod 8; workgroups are dispatched
+// round-robin over the 8 XCDs) owns one contiguous region of rows, and the
+// XCD's workgroups sweep that region together, one pass of RP*16 rows each per
+// step.  The rows an XCD works on at any moment, and the block rows they gather
+// (neighbours in a stencil ordering), then stay within a window that fits its
+// L2.  Layout: 16 lanes per row (a DPP row), lane owning columns lane + 16 j.
+// The row's (column, value) pairs are loaded cooperatively, 8 at a time (lane
+// u & 7 loads entry u), and handed to the whole row by DPP broadcasts, so each
+// nonzero costs one block-row read per lane and no per-lane index loads.
 template <class T, int J, class Epi>
-__global__ __launch_bounds__(kBlock) void k_spmm_csr(const Ctl* ctl, CsrOp<T> A, Layout ly, int rows_per_chunk,
+__global__ __launch_bounds__(kBlock) void k_spmm_csr(const Ctl* ctl, CsrOp<T> A, Layout ly, int rows_per_xcd,
                                                       const T* __restrict__ X, T* __restrict__ Y, Epi epi) {
     if (stopped(ctl)) return;
-    const int tid = threadIdx.x;
-    const int lane = tid & (ly.L - 1);
-    const int grp = tid >> ly.lgL;
-    const int rpb = kBlock >> ly.lgL;
-    const int chunk = xcd_chunk(blockIdx.x, gridDim.x);
-    const int r0 = chunk * rows_per_chunk;
-    const int r1 = min(A.n, r0 + rows_per_chunk);
+    constexpr int RP = J == 1 ? 2 : 1;
+    constexpr int U = 8;
+    const int lane = threadIdx.x & 15;
+    const int grp = threadIdx.x >> 4;
+    const int xcd = blockIdx.x & 7, q = blockIdx.x >> 3, nq = gridDim.x >> 3;
+    const int r0 = xcd * rows_per_xcd;
+    const int r1 = min(A.n, r0 + rows_per_xcd);
     const int s = ly.s;
+    int col[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) col[j] = min(lane + 16 * j, s - 1);
     typename Epi::St st;
     epi.init(st);
-    for (int base = r0; base < r1; base += rpb) {
-        const int i = base + grp;
-        const bool valid = i < r1;
-        T acc[J];
+    for (int base = r0 + q * RP * 16; base < r1; base += nq * RP * 16) {
+        int i[RP], k0[RP], k1[RP];
+        bool valid[RP];
 #pragma unroll
-        for (int j = 0; j < J; ++j) acc[j] = zero<T>();
-        if (valid) {
-            const int k0 = A.rp[i], k1 = A.rp[i + 1];
-            for (int k = k0; k < k1; ++k) {
-                const int c = A.ci[k];
-                const T a = A.va[k];
-                const T* __restrict__ xr = X + (size_t)c * s;
+        for (int p = 0; p < RP; ++p) {
+            i[p] = base + p * 16 + grp;
+            valid[p] = i[p] < r1;
+            k0[p] = valid[p] ? A.rp[i[p]] : 0;
+            k1[p] = valid[p] ? A.rp[i[p] + 1] : 0;
+        }
+        T acc[RP][J];
 #pragma unroll
-                for (int j = 0; j < J; ++j) {
-                    int col = lane + ly.L * j;
-                    if (col < s) acc[j] = fma_(a, xr[col], acc[j]);
-                }
+        for (int p = 0; p < RP; ++p)
+#pragma unroll
+            for (int j = 0; j < J; ++j) acc[p][j] = zero<T>();
+        for (int off = 0;; off += U) {
+            int mc[RP];
+            T ma[RP];
+            bool more = false;
+#pragma unroll
+            for (int p = 0; p < RP; ++p) {
+                const int k = k0[p] + off + (lane & (U - 1));
+                const int kc = max(0, min(k, k1[p] - 1));   // clamped: always a valid entry
+                mc[p] = A.ci[kc];
+                const T v = A.va[kc];
+                ma[p] = k < k1[p] ? v : zero<T>();
+                more |= k0[p] + off + U < k1[p];
             }
 #pragma unroll
-            for (int j = 0; j < J; ++j) {
-                int col = lane + ly.L * j;
-                if (col < s) Y[(size_t)i * s + col] = acc[j];
+            for (int p = 0; p < RP; ++p) {
+                sfor<0, U>([&](auto ic) {
+                    constexpr int u = decltype(ic)::value;
+                    const int c = rbc32<u>(mc[p]);
+                    const T a = rbc64<u>(ma[p]);
+                    const T* __restrict__ xr = X + (size_t)c * s;
+#pragma unroll
+                    for (int j = 0; j < J; ++j) acc[p][j] = fma_(a, xr[col[j]], acc[p][j]);
+                });
+            }
+            if (!more) break;
+        }
+#pragma unroll
+        for (int p = 0; p < RP; ++p) {
+            if (valid[p]) {
+#pragma unroll
+                for (int j = 0; j < J; ++j)
+                    if (lane + 16 * j < s) Y[(size_t)i[p] * s + lane + 16 * j] = acc[p][j];
             }
         }
-        epi.row(st, i, valid, lane, ly, acc);
+#pragma unroll
+        for (int p = 0; p < RP; ++p) epi.row(st, i[p], valid[p], lane, ly, acc[p]);
     }
     epi_finish<Epi, J>(epi, st, blockIdx.x, s);
 }

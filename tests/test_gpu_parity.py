@@ -107,12 +107,12 @@ def test_block_qr(pkg, ctx, kind, s):
 def test_block_qr_ill_conditioned_uses_shift(pkg, ctx):
     rng = np.random.default_rng(3)
     U, _ = np.linalg.qr(rng.standard_normal((4000, 8)))
-    Z = U @ np.diag(10.0 ** -np.arange(8) * 1.5) @ np.linalg.qr(rng.standard_normal((8, 8)))[0]
+    Z = U @ np.diag(np.logspace(0, -9, 8)) @ np.linalg.qr(rng.standard_normal((8, 8)))[0]
+    assert np.linalg.cond(Z) > 1e8       # kappa^2 u > 1: the unshifted Cholesky of Z^T Z fails
     Q, Cm, rc = pkg.block_qr(ctx, Z)
     assert rc == 0
-    # kappa(Z) ~ 1e10: plain CholeskyQR2 would fail; the shifted pass keeps Q
-    # orthonormal to ~1e-10 and the factorisation exact to rounding
-    np.testing.assert_allclose(Q.T @ Q, np.eye(8), atol=1e-10)
+    # the shifted first pass plus two plain passes keep Q orthonormal
+    np.testing.assert_allclose(Q.T @ Q, np.eye(8), atol=1e-12)
     np.testing.assert_allclose(Q @ Cm, Z, atol=1e-13)
 
 
