@@ -40,12 +40,12 @@ def spmm_roofline(pkg, ctx, A, n, nnz, s, stream, reps=50):
     torch.cuda.synchronize()
     with torch.cuda.stream(stream):
         for _ in range(5):
-            pkg.spmm(ctx, A, X, Y)
+            pkg.spmm(ctx, A, X, Y, sync=False)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         for _ in range(reps):
-            pkg.spmm(ctx, A, X, Y)
+            pkg.spmm(ctx, A, X, Y, sync=False)
         e1.record(stream)
     e1.synchronize()
     ms = e0.elapsed_time(e1) / reps
@@ -91,6 +91,9 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--mixed-steps", type=int, default=1)
+    ap.add_argument("--maxit", type=int, default=2000,
+                    help="iteration cap per solve (the converging methods need 250-450 here)")
     ap.add_argument("--spmm-only", action="store_true",
                     help="only the sparse x block kernel and a plain device copy of one block "
                          "(the workload of the hardware-counter runs)")
@@ -132,7 +135,7 @@ def main():
     def solve_all(per_method=None):
         for m in METHODS:
             tm = time.perf_counter()
-            X, info = pkg.solve(ctx, A, B, m, X=Xs[m], x0_zero=True, tol=args.tol, maxit=20000)
+            X, info = pkg.solve(ctx, A, B, m, X=Xs[m], x0_zero=True, tol=args.tol, maxit=args.maxit)
             if per_method is not None:
                 torch.cuda.synchronize()
                 per_method[m] += time.perf_counter() - tm
@@ -157,6 +160,23 @@ def main():
     ms_per_step = 1e3 * total / args.steps
     value = len(METHODS) * s / (total / args.steps)
 
+    # the same step with FP32 inner solves inside FP64 iterative refinement
+    mixed = {}
+    t_mixed = 0.0
+    if args.mixed_steps > 0:
+        for k in range(args.mixed_steps):
+            for m in METHODS:
+                tm = time.perf_counter()
+                X, info = pkg.solve(ctx, A, B, m, X=Xs[m], x0_zero=True, tol=args.tol, maxit=args.maxit,
+                                    precision="fp32_refine", inner_tol=1e-4, max_outer=20)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - tm
+                t_mixed += dt
+                mixed[m] = {"status": info.status_name, "outer": info.outer_iterations,
+                            "inner_iterations": info.iterations, "rel_res_true": info.rel_res_true,
+                            "s_per_solve": round(dt, 4), "rhs_per_s": round(s / dt, 3)}
+        log("mixed step: " + ", ".join(f"{m} {mixed[m]['status']} outer={mixed[m]['outer']}" for m in METHODS))
+
     roof = spmm_roofline(pkg, ctx, A, n, nnz, s, stream)
     gpu_iters = {m: infos[m][1].iterations for m in METHODS}
     out = {
@@ -165,7 +185,8 @@ def main():
         "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"convdiff3d-{args.grid}^3-s16", "n": n, "nnz": nnz, "s": s,
-                   "methods": list(METHODS), "tol": args.tol, "format": "csr", "precision": "fp64",
+                   "methods": list(METHODS), "tol": args.tol, "maxit": args.maxit, "format": "csr",
+                   "precision": "fp64",
                    "rhs_per_step": len(METHODS) * s},
         "per_method": {m: {"iterations": infos[m][1].iterations, "status": infos[m][1].status_name,
                            "rel_res_true": infos[m][1].rel_res_true,
@@ -173,6 +194,10 @@ def main():
                            "rhs_per_s": round(s / (per_method[m] / args.steps), 3)} for m in METHODS},
         "roofline": roof,
     }
+    if args.mixed_steps > 0:
+        ok = sum(s for m in METHODS if mixed[m]["status"] == "ok")
+        out["mixed_fp32_refine"] = {"value": round(ok / (t_mixed / args.mixed_steps), 4), "unit": "RHS/s",
+                                    "per_method": mixed}
     if not args.no_cpu:
         prob = inputs.Problem("convdiff3d", A_csr, B_np, METHODS, {})
         out["cpu_baseline"] = cpu_baseline(prob, gpu_iters, args.cpu_iters)

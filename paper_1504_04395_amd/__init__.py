@@ -10,3 +10,11 @@ from ._binding import (  # noqa: F401
     LIB_PATH, METHODS, PRECISIONS, STATUS_NAMES, Context, Matrix, SkrError, SolveInfo, block_qr, load_library,
     opts_default, sddmm, solve, spmm,
 )
+
+
+def __getattr__(name):
+    # the autograd wrapper imports torch; load it on first use only
+    if name in ("SparseSolve", "sparse_solve"):
+        from . import autograd
+        return getattr(autograd, name)
+    raise AttributeError(name)

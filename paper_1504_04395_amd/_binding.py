@@ -105,6 +105,17 @@ def _is_torch(x):
     return type(x).__module__.startswith("torch")
 
 
+def _order_torch(*xs):
+    """Wait for torch's current stream when any argument is a CUDA tensor, so
+    that the library's stream sees finished inputs."""
+    for x in xs:
+        if _is_torch(x) and x.is_cuda:
+            import torch
+            torch.cuda.current_stream().synchronize()
+            return True
+    return False
+
+
 def _ptr_mem(x):
     """(pointer, mem kind, dtype code, keepalive)."""
     if _is_torch(x):
@@ -193,6 +204,7 @@ class Matrix:
         return cls(ctx, csr.n, csr.indptr, csr.indices, csr.data, **kw)
 
     def update_values(self, data):
+        _order_torch(data)
         p, mem, _, keep = _ptr_mem(data)
         _check(self.ctx, load_library().skr_matrix_update_values(self.handle, _VP(p), mem))
 
@@ -260,6 +272,7 @@ def solve(ctx: Context, A: Matrix, B, method: str, X=None, x0_zero: bool = False
     pX, memX, _, _ = _ptr_mem(X)
     if memX != memB:
         raise ValueError("B and X must live in the same memory")
+    _order_torch(B, X)
     o = opts_default()
     o.tol = tol
     o.maxit = maxit
@@ -283,8 +296,9 @@ def solve(ctx: Context, A: Matrix, B, method: str, X=None, x0_zero: bool = False
     return X, info
 
 
-def spmm(ctx: Context, A: Matrix, X, Y=None, adjoint: bool = False):
-    """skr_spmm: Y = A X (or A^H X)."""
+def spmm(ctx: Context, A: Matrix, X, Y=None, adjoint: bool = False, sync: bool = True):
+    """skr_spmm: Y = A X (or A^H X).  With device tensors and sync=False the
+    product is only enqueued on the context's stream (the caller orders it)."""
     pX, mem, dt, keep = _ptr_mem(X)
     n, s = X.shape
     if Y is None:
@@ -294,7 +308,12 @@ def spmm(ctx: Context, A: Matrix, X, Y=None, adjoint: bool = False):
         else:
             Y = np.empty_like(keep)
     pY, _, _, _ = _ptr_mem(Y)
+    if sync:
+        _order_torch(X, Y)
     _check(ctx, load_library().skr_spmm(ctx.handle, A.handle, s, _VP(pX), s, _VP(pY), s, mem, int(adjoint)))
+    if sync and mem == SKR_MEM_DEVICE:
+        import torch
+        torch.cuda.synchronize()
     return Y
 
 
@@ -310,7 +329,11 @@ def sddmm(ctx: Context, A: Matrix, G, X, scale: float = -1.0, out=None):
         else:
             out = np.empty(A.nnz, dtype=kg.dtype)
     pO, _, _, _ = _ptr_mem(out)
+    _order_torch(G, X, out)
     _check(ctx, load_library().skr_sddmm(ctx.handle, A.handle, s, _VP(pG), _VP(pX), _VP(pO), scale, mem))
+    if mem == SKR_MEM_DEVICE:
+        import torch
+        torch.cuda.synchronize()
     return out
 
 
@@ -324,6 +347,7 @@ def block_qr(ctx: Context, Z):
     else:
         Q = np.empty_like(kz)
     pQ, _, _, _ = _ptr_mem(Q)
+    _order_torch(Z, Q)
     C = np.zeros(s * s * (2 if dt == SKR_C64 else 1), dtype=np.float64)
     rc = load_library().skr_block_qr(ctx.handle, n, s, dt, _VP(pZ), _VP(pQ),
                                      C.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), mem)

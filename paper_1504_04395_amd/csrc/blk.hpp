@@ -495,8 +495,14 @@ __device__ inline void set_bd(Ctl* c) { set_breakdown(c); }
 // pass 1: G = Z^H Z -> S1 (shifted if the plain factorisation fails), S1^{-1};
 // pass 2: G = Q1^H Q1 -> S2, S2^{-1}; S12 = S2 S1, the R factor S = S12 unless shifted;
 // pass 3 (shifted case only): G = Q2^H Q2 -> S3, S3^{-1}; S = S3 S12.
+// `u` is the unit roundoff of the stored blocks (2^-53 for FP64, 2^-24 for the
+// FP32 inner solves).  The Gram itself is always accumulated in FP64, so the
+// shift that makes the Cholesky factorisation succeed is Fukaya et al.'s
+// 11 (ns + s(s+1)) 2^-53 tr(G); it is raised to 1e3 u tr(G) where that is
+// larger, so that the shifted Q1 (condition number <= (1e3 u)^{-1/2}) is still
+// orthonormal enough, in the stored precision, for the two passes after it.
 __global__ void k_qr_chol(Ctl* c, int slot, int pass, int n, int s, const c64* __restrict__ part2, int p2,
-                          c64* __restrict__ mats) {
+                          c64* __restrict__ mats, double u) {
     if (stopped(c)) return;
     if (pass == 3 && !c->qr_shift[slot]) return;
     extern __shared__ c64 dyn[];
@@ -517,13 +523,13 @@ __global__ void k_qr_chol(Ctl* c, int slot, int pass, int n, int s, const c64* _
     if (pass == 1) {
         if (threadIdx.x == 0) c->qr_shift[slot] = 0;
         sm_copy(A, G, ss);
-        int ok = sm_cholesky(A, s, 0.0, &flag);
+        int ok = sm_cholesky(A, s, 0.0, &flag, 1e4 * u);
         if (!ok) {
             double trg = 0.0;
             for (int i = 0; i < s; ++i) trg += G[i * s + i].x;
-            double shift = 11.0 * ((double)n * s + (double)s * (s + 1)) * 0x1p-53 * trg;
+            double shift = fmax(11.0 * ((double)n * s + (double)s * (s + 1)) * 0x1p-53, 1e3 * u) * trg;
             sm_copy(A, G, ss);
-            ok = sm_cholesky(A, s, shift, &flag);
+            ok = sm_cholesky(A, s, shift, &flag, fmax(1e2 * u, 1e-12));
             if (threadIdx.x == 0) c->qr_shift[slot] = 1;
             __syncthreads();
         }
@@ -539,7 +545,7 @@ __global__ void k_qr_chol(Ctl* c, int slot, int pass, int n, int s, const c64* _
         return;
     }
     sm_copy(A, G, ss);
-    int ok = sm_cholesky(A, s, 0.0, &flag);
+    int ok = sm_cholesky(A, s, 0.0, &flag, fmax(1e2 * u, 1e-12));
     if (!ok) {
         if (threadIdx.x == 0) set_bd(c);
         return;

@@ -161,24 +161,25 @@ inline size_t mat_lds(int s, int nmat, int ntile) {
 template <class T, int J>
 void cholqr(Env<T>& e, int slot, const T* Z, T* Q, int mode, const T* Other) {
     const int s = e.s, ss = s * s;
+    const double u = sizeof(typename Tr<T>::R) == 4 ? 0x1p-24 : 0x1p-53;   // stored precision
     size_t lds4 = 4 * (size_t)ss * sizeof(c64);
     size_t ldsT = mat_lds(s, 3, 1);
     reduce2(e, ss);
-    k_qr_chol<<<1, kScalar, lds4, e.st>>>(e.ctl, slot, 1, e.n, s, e.part2, e.p2, e.mats);
+    k_qr_chol<<<1, kScalar, lds4, e.st>>>(e.ctl, slot, 1, e.n, s, e.part2, e.p2, e.mats, u);
     SKR_LAUNCHED();
     // Gram of Q1 = Z S1^{-1}
     k_bl_tri<T, J><<<e.nb, kBlock, ldsT, e.st>>>(e.ctl, slot, 0, 1, 0, e.tl, TRI_G_OUT_OUT, e.mats, Z, nullptr,
                                                  nullptr, e.part);
     SKR_LAUNCHED();
     reduce2(e, ss);
-    k_qr_chol<<<1, kScalar, lds4, e.st>>>(e.ctl, slot, 2, e.n, s, e.part2, e.p2, e.mats);
+    k_qr_chol<<<1, kScalar, lds4, e.st>>>(e.ctl, slot, 2, e.n, s, e.part2, e.p2, e.mats, u);
     SKR_LAUNCHED();
     // shifted case only: Gram of Q2 = Z S1^{-1} S2^{-1}
     k_bl_tri<T, J><<<e.nb, kBlock, ldsT, e.st>>>(e.ctl, slot, 1, 2, 0, e.tl, TRI_G_OUT_OUT, e.mats, Z, nullptr,
                                                  nullptr, e.part);
     SKR_LAUNCHED();
     reduce2(e, ss, slot);
-    k_qr_chol<<<1, kScalar, lds4, e.st>>>(e.ctl, slot, 3, e.n, s, e.part2, e.p2, e.mats);
+    k_qr_chol<<<1, kScalar, lds4, e.st>>>(e.ctl, slot, 3, e.n, s, e.part2, e.p2, e.mats, u);
     SKR_LAUNCHED();
     // Q = Z S1^{-1} S2^{-1} [S3^{-1}]
     k_bl_tri<T, J><<<e.nb, kBlock, ldsT, e.st>>>(e.ctl, slot, 0, 2, 1, e.tl, mode | TRI_WRITE, e.mats, Z, Q, Other,

@@ -663,18 +663,23 @@ int solve_mixed(skr_context* c, skr_matrix* M, int s, const T* B, T* X, bool x0z
             bd = iters;
             break;
         }
-        InnerStats st = iterate<L>(c, f, m, method, o.inner_tol, o.maxit, o.check_every, o.use_graph != 0,
+        // inner target: inner_tol, relaxed on the last step to what is still
+        // needed (half of tol / current relative residual), never above 0.5
+        const double inner = std::max(o.inner_tol, std::min(0.5, 0.5 * o.tol / rel));
+        InnerStats st = iterate<L>(c, f, m, method, inner, o.maxit, o.check_every, o.use_graph != 0,
                                    fnv(&ar, sizeof(ar), 1));
         iters += st.iters;
         mv += st.matvecs + s;  // + the outer residual product
         rres = st.rres;
-        k_xupd<T, L, J><<<e.nb, kBlock, mat_lds(s, 1, 1), e.st>>>(e.tl, f.mats, pre ? M_RB : -1, X, d32, 0);
-        SKR_LAUNCHED();
-        if (st.status == SKR_BREAKDOWN && st.iters == 0) {
+        if (!(st.rres < 1.0) || !std::isfinite(st.rres)) {
+            // the inner solve made no progress (e.g. it diverged in FP32): keep
+            // the current X and stop
             status = SKR_BREAKDOWN;
             bd = iters;
             break;
         }
+        k_xupd<T, L, J><<<e.nb, kBlock, mat_lds(s, 1, 1), e.st>>>(e.tl, f.mats, pre ? M_RB : -1, X, d32, 0);
+        SKR_LAUNCHED();
     }
     res->status = status;
     if (status != SKR_BREAKDOWN && rel > 1.0) res->status = SKR_DIVERGED;

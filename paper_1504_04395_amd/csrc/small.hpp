@@ -162,10 +162,11 @@ __device__ inline void sm_lu_solve_h(const c64* LU, const int* piv, c64* B, int 
 // In-place upper Cholesky factor G = S^H S of a Hermitian matrix (upper
 // triangle of G is used; the strict lower triangle is set to 0).  `shift` is
 // added to the diagonal first.  Returns 1 on success, 0 if a pivot is not
-// safely positive (d <= 1e-12 * largest original diagonal entry, i.e. a
-// condition number beyond ~1e6, or not finite): past that point a second
-// CholeskyQR pass no longer restores orthogonality to rounding level.
-__device__ inline int sm_cholesky(c64* G, int s, double shift, int* flag /* shared */) {
+// safely positive (d <= tau * largest original diagonal entry, or not finite).
+// CholeskyQR callers pass tau = 1e4 u for the first pass (u = unit roundoff of
+// the stored block: a condition number beyond (1e4 u)^{-1/2} would leave the
+// first-pass Q too far from orthonormal for a second pass to repair).
+__device__ inline int sm_cholesky(c64* G, int s, double shift, int* flag /* shared */, double tau) {
     __shared__ double diag0[kMaxS];
     for (int i = threadIdx.x; i < s; i += blockDim.x) {
         G[i * s + i].x += shift;
@@ -178,7 +179,7 @@ __device__ inline int sm_cholesky(c64* G, int s, double shift, int* flag /* shar
     for (int i = 0; i < s; ++i) dmax = fmax(dmax, diag0[i]);
     for (int k = 0; k < s; ++k) {
         double d = G[k * s + k].x;
-        bool bad = !(d > 1e-12 * dmax) || !isfinite(d) || !(diag0[k] > 0.0);
+        bool bad = !(d > tau * dmax) || !isfinite(d) || !(diag0[k] > 0.0);
         if (bad) {
             if (threadIdx.x == 0) *flag = 0;
             __syncthreads();
