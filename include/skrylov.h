@@ -94,8 +94,10 @@ typedef struct {
     int32_t use_graph;      /* replay the m-iteration schedule as a hipGraph     [1]     */
 } skr_opts;
 
-/* Result record.  history is caller-owned (may be NULL): on return it holds
- * ||R_k||_F / ||R_0||_F for k = 0..history_len-1 of the (last inner) solve. */
+/* Result record.  history is caller-owned (may be NULL).  FP64 solves: on
+ * return it holds the recursive ||R_k||_F / ||R_0||_F for k = 0..history_len-1.
+ * FP32 + refinement: it holds the true FP64 relative residual ||B - A X||_F /
+ * ||B||_F before each outer step and after the last one. */
 typedef struct {
     int32_t status;             /* skr_status of the solve                      */
     int32_t iterations;         /* completed iterations (sum over inner solves) */
