@@ -214,25 +214,30 @@ __global__ __launch_bounds__(kBlock) void k_bl_gram(const Ctl* ctl, Tile16 tl, c
     g.store(tl.s, lds, part + (size_t)blockIdx.x * tl.s * tl.s);
 }
 
-// Stage-2 reduction of per-workgroup partials [np][E] -> [gridDim.y][E]
+// Second reduction stage: per-workgroup partials [np][E] -> out[E].  One wave
+// per element: lane l sums partials l, l + 64, l + 128, ... into eight
+// independent accumulators (so eight loads are in flight), then the wave sums
+// its lanes by a butterfly.  The order is fixed, so results are reproducible.
 __global__ __launch_bounds__(kBlock) void k_reduce_parts(const Ctl* ctl, int cond_slot, const c64* __restrict__ part,
                                                          int np, int E, c64* __restrict__ out) {
     if (stopped(ctl)) return;
     if (cond_slot >= 0 && !ctl->qr_shift[cond_slot]) return;
-    const int e = blockIdx.x * kBlock + threadIdx.x;
-    if (e >= E) return;
-    const int per = (np + gridDim.y - 1) / gridDim.y;
-    const int b0 = blockIdx.y * per, b1 = min(np, b0 + per);
-    c64 a0 = {0.0, 0.0}, a1 = {0.0, 0.0}, a2 = {0.0, 0.0}, a3 = {0.0, 0.0};
-    int b = b0;
-    for (; b + 4 <= b1; b += 4) {
-        a0 = a0 + part[(size_t)b * E + e];
-        a1 = a1 + part[(size_t)(b + 1) * E + e];
-        a2 = a2 + part[(size_t)(b + 2) * E + e];
-        a3 = a3 + part[(size_t)(b + 3) * E + e];
+    const int e = blockIdx.x * kWaves + (threadIdx.x >> 6);
+    if (e >= E) return;   // uniform per wave
+    const int l = threadIdx.x & 63;
+    c64 a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = {0.0, 0.0};
+    int b = l;
+    for (; b + 7 * 64 < np; b += 8 * 64) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = a[u] + part[(size_t)(b + 64 * u) * E + e];
     }
-    for (; b < b1; ++b) a0 = a0 + part[(size_t)b * E + e];
-    out[(size_t)blockIdx.y * E + e] = (a0 + a1) + (a2 + a3);
+    for (; b < np; b += 64) a[0] = a[0] + part[(size_t)b * E + e];
+    c64 t = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    t.x = wave_sum(t.x);
+    t.y = wave_sum(t.y);
+    if (l == 0) out[e] = t;
 }
 
 // final sum of the stage-2 partials into LDS
@@ -329,6 +334,254 @@ __global__ __launch_bounds__(kBlock) void k_bl_tri(const Ctl* ctl, int slot, int
         __syncthreads();
         g.store(s, dyn, part + (size_t)blockIdx.x * s * s);
     }
+}
+
+// ------------------------------------------------ real s <= 16: MFMA row tiles
+// A wave owns 16 consecutive rows.  Lane L = c + 16 q holds, in register v, the
+// element (row 4v + q, column c) of the tile: four coalesced 16-column loads,
+// and also the layout of an MFMA f64 16x16x4 result, D[4v + q][c] in lane
+// c + 16 q, register v.  The product of the tile with an s x s matrix M is
+// four MFMAs whose A operand (lane c + 16 q: tile[c][4t + q]) is read back
+// transposed through a per-wave LDS tile, and whose B operand (lane c + 16 q:
+// M[4t + q][c]) stays in registers.  Padding rows and columns are zero.
+constexpr int kTileLd = 17;   // padded LDS row: transposed reads are bank-spread
+
+// B operand of M (complex FP64 storage, real part) for the four k-slabs
+__device__ inline void mfma_bop(const c64* __restrict__ Mg, int s, int c, int q, double (&m)[4]) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int k = 4 * t + q;
+        m[t] = (k < s && c < s) ? Mg[k * s + c].x : 0.0;
+    }
+}
+// returns X M for the wave's tile X (x[v] = X[4v + q][c]); tw: this wave's LDS tile
+__device__ inline d4 mfma_apply(const double (&x)[4], const double (&m)[4], double* tw, int c, int q) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) tw[(4 * v + q) * kTileLd + c] = x[v];
+    __builtin_amdgcn_wave_barrier();
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(tw[c * kTileLd + 4 * t + q], m[t], acc, 0, 0, 0);
+    __builtin_amdgcn_wave_barrier();
+    return acc;
+}
+// the wave's tile rows of P (row stride s) as x[v] = P[b + 4v + q][c]; zero
+// outside rows [b, r1) and columns [0, s).  Loads are clamped, not branched.
+template <class T>
+__device__ inline void tile_load(const T* P, int b, int r1, int s, int c, int q, double (&x)[4]) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int i = b + 4 * v + q;
+        const bool ok = i < r1 && c < s;
+        const double val = (double)P[(size_t)(ok ? i : b) * s + (ok ? c : 0)];
+        x[v] = ok ? val : 0.0;
+    }
+}
+template <class T>
+__device__ inline void tile_store(T* P, int b, int r1, int s, int c, int q, const d4& x) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int i = b + 4 * v + q;
+        if (i < r1 && c < s) P[(size_t)i * s + c] = (T)x[v];
+    }
+}
+
+// k_bl_tri for real blocks with s <= 16 (same arguments and results).
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_bl_tri16(const Ctl* ctl, int slot, int cond, int nchain, int add_shift,
+                                                     Tile16 tl, int mode, const c64* __restrict__ mats, const T* Z,
+                                                     T* Out, const T* __restrict__ Other, c64* part) {
+    if (stopped(ctl)) return;
+    const int shifted = ctl->qr_shift[slot];
+    if (cond && !shifted) return;
+    const int nc = nchain + (add_shift && shifted ? 1 : 0);
+    const int s = tl.s, ss = s * s;
+    const int base = slot == 0 ? M_S1 : M_T1;
+    const int L = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int c = L & 15, q = L >> 4;
+    double m0[4], m1[4], m2[4];
+    mfma_bop(mats + (size_t)(base + 1) * ss, s, c, q, m0);
+    mfma_bop(mats + (size_t)(base + 3) * ss, s, c, q, m1);
+    mfma_bop(mats + (size_t)(base + 5) * ss, s, c, q, m2);
+    __shared__ double tiles[kWaves][16 * kTileLd];
+    __shared__ c64 glds[256];
+    double* tw = tiles[w];
+    GramAcc<1, false> g;
+    g.clear();
+    const int r0 = xcd_chunk(blockIdx.x, gridDim.x) * tl.rpc;
+    const int r1 = min(tl.n, r0 + tl.rpc);
+    for (int b = r0 + 16 * w; b < r1; b += 16 * kWaves) {
+        double x[4];
+        tile_load<T>(Z, b, r1, s, c, q, x);
+        d4 o = mfma_apply(x, m0, tw, c, q);
+        if (nc > 1) {
+            double y[4] = {o[0], o[1], o[2], o[3]};
+            o = mfma_apply(y, m1, tw, c, q);
+        }
+        if (nc > 2) {
+            double y[4] = {o[0], o[1], o[2], o[3]};
+            o = mfma_apply(y, m2, tw, c, q);
+        }
+        if (mode & TRI_WRITE) tile_store<T>(Out, b, r1, s, c, q, o);
+        if (mode & (TRI_G_OUT_OUT | TRI_G_OTHER_OUT | TRI_G_OUT_OTHER)) {
+            double ot[4];
+            if (mode & (TRI_G_OTHER_OUT | TRI_G_OUT_OTHER)) tile_load<T>(Other, b, r1, s, c, q, ot);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const double ov[1] = {o[v]};
+                if (mode & TRI_G_OUT_OUT) {
+                    g.add(ov, ov);
+                } else {
+                    const double tv[1] = {ot[v]};
+                    if (mode & TRI_G_OTHER_OUT) g.add(tv, ov);
+                    else g.add(ov, tv);
+                }
+            }
+        }
+    }
+    if (mode & (TRI_G_OUT_OUT | TRI_G_OTHER_OUT | TRI_G_OUT_OTHER)) {
+        __syncthreads();
+        g.store(s, glds, part + (size_t)blockIdx.x * s * s);
+    }
+}
+
+// k_bl_axpm for real blocks with s <= 16 (same arguments and results).
+template <class T, bool GRAM>
+__global__ __launch_bounds__(kBlock) void k_bl_axpm16(const Ctl* ctl, Tile16 tl, const c64* __restrict__ mats,
+                                                      int mslot, const c64* __restrict__ sc, int gslot, const T* A,
+                                                      const T* B, const T* __restrict__ Cm, T* Out, c64* part) {
+    if (stopped(ctl)) return;
+    const int s = tl.s;
+    const int L = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int c = L & 15, q = L >> 4;
+    double m[4];
+    mfma_bop(mats + (size_t)mslot * s * s, s, c, q, m);
+    const double gamma = Cm ? sc[gslot].x : 0.0;
+    __shared__ double tiles[kWaves][16 * kTileLd];
+    __shared__ c64 glds[256];
+    double* tw = tiles[w];
+    GramAcc<1, false> g;
+    g.clear();
+    const int r0 = xcd_chunk(blockIdx.x, gridDim.x) * tl.rpc;
+    const int r1 = min(tl.n, r0 + tl.rpc);
+    for (int b = r0 + 16 * w; b < r1; b += 16 * kWaves) {
+        double x[4], a[4] = {0.0, 0.0, 0.0, 0.0};
+        tile_load<T>(B, b, r1, s, c, q, x);
+        if (Cm) {
+            double y[4];
+            tile_load<T>(Cm, b, r1, s, c, q, y);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) x[v] = fma(gamma, y[v], x[v]);
+        }
+        if (A) tile_load<T>(A, b, r1, s, c, q, a);
+        d4 o = mfma_apply(x, m, tw, c, q);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) o[v] += a[v];
+        tile_store<T>(Out, b, r1, s, c, q, o);
+        if (GRAM) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const double ov[1] = {o[v]};
+                g.add(ov, ov);
+            }
+        }
+    }
+    if (GRAM) {
+        __syncthreads();
+        g.store(s, glds, part + (size_t)blockIdx.x * s * s);
+    }
+}
+
+// k_blrq_updz for real blocks with s <= 16.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_blrq_updz16(const Ctl* ctl, Tile16 tl, const c64* __restrict__ mats,
+                                                        T* __restrict__ X, const T* __restrict__ Vb,
+                                                        const T* __restrict__ Q, const T* __restrict__ W,
+                                                        T* __restrict__ Z, c64* part) {
+    if (stopped(ctl)) return;
+    const int s = tl.s;
+    const int L = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int c = L & 15, q = L >> 4;
+    double ma[4], mac[4];
+    mfma_bop(mats + (size_t)M_ALPHA * s * s, s, c, q, ma);     // -alpha
+    mfma_bop(mats + (size_t)M_ALPHAC * s * s, s, c, q, mac);   // alpha C
+    __shared__ double tiles[kWaves][16 * kTileLd];
+    __shared__ c64 glds[256];
+    double* tw = tiles[w];
+    GramAcc<1, false> g;
+    g.clear();
+    const int r0 = xcd_chunk(blockIdx.x, gridDim.x) * tl.rpc;
+    const int r1 = min(tl.n, r0 + tl.rpc);
+    for (int b = r0 + 16 * w; b < r1; b += 16 * kWaves) {
+        double v[4], wv[4], x[4], z[4];
+        tile_load<T>(Vb, b, r1, s, c, q, v);
+        tile_load<T>(W, b, r1, s, c, q, wv);
+        tile_load<T>(X, b, r1, s, c, q, x);
+        tile_load<T>(Q, b, r1, s, c, q, z);
+        d4 xo = mfma_apply(v, mac, tw, c, q);
+        d4 zo = mfma_apply(wv, ma, tw, c, q);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            xo[u] += x[u];
+            zo[u] += z[u];
+        }
+        tile_store<T>(X, b, r1, s, c, q, xo);
+        tile_store<T>(Z, b, r1, s, c, q, zo);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double zv[1] = {zo[u]};
+            g.add(zv, zv);
+        }
+    }
+    __syncthreads();
+    g.store(s, glds, part + (size_t)blockIdx.x * s * s);
+}
+
+// k_blst_upd for real blocks with s <= 16.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_blst_upd16(const Ctl* ctl, Tile16 tl, const c64* __restrict__ mats,
+                                                       const c64* __restrict__ sc, T* __restrict__ X,
+                                                       const T* __restrict__ U, const T* __restrict__ St,
+                                                       const T* __restrict__ Tt, T* __restrict__ Z, c64* part) {
+    if (stopped(ctl)) return;
+    const int s = tl.s;
+    const int L = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int c = L & 15, q = L >> 4;
+    double mac[4], mwc[4];
+    mfma_bop(mats + (size_t)M_AC * s * s, s, c, q, mac);   // a C
+    mfma_bop(mats + (size_t)M_WC * s * s, s, c, q, mwc);   // omega C
+    const double mw = -sc[SC_OMEGA].x;
+    __shared__ double tiles[kWaves][16 * kTileLd];
+    __shared__ c64 glds[256];
+    double* tw = tiles[w];
+    GramAcc<1, false> g;
+    g.clear();
+    const int r0 = xcd_chunk(blockIdx.x, gridDim.x) * tl.rpc;
+    const int r1 = min(tl.n, r0 + tl.rpc);
+    for (int b = r0 + 16 * w; b < r1; b += 16 * kWaves) {
+        double u[4], st[4], tt[4], x[4];
+        tile_load<T>(U, b, r1, s, c, q, u);
+        tile_load<T>(St, b, r1, s, c, q, st);
+        tile_load<T>(Tt, b, r1, s, c, q, tt);
+        tile_load<T>(X, b, r1, s, c, q, x);
+        d4 xa = mfma_apply(u, mac, tw, c, q);
+        d4 xb = mfma_apply(st, mwc, tw, c, q);
+        d4 z;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            xa[v] = (x[v] + xa[v]) + xb[v];
+            z[v] = fma(mw, tt[v], st[v]);
+        }
+        tile_store<T>(X, b, r1, s, c, q, xa);
+        tile_store<T>(Z, b, r1, s, c, q, z);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const double zv[1] = {z[v]};
+            g.add(zv, zv);
+        }
+    }
+    __syncthreads();
+    g.store(s, glds, part + (size_t)blockIdx.x * s * s);
 }
 
 // Out = A + (B + gamma C) M  [+ part = Out^H Out]; A or C may be null; Out may alias A or B.
@@ -729,13 +982,15 @@ __global__ void k_blst_omega(Ctl* c, int s, const c64* __restrict__ part2, int p
     __syncthreads();
     sm_copy(A, mats + (size_t)M_C * ss, ss);
     sm_gemm(K, A, 0, A, 1, s);                 // C C^H
+    c64 num = {0.0, 0.0}, den = {0.0, 0.0};   // tr(G1 K), tr(G2 K)
+    for (int e = threadIdx.x; e < ss; e += blockDim.x) {
+        const int a = e / s, b = e - a * s;
+        num = num + G1[e] * K[b * s + a];
+        den = den + G2[e] * K[b * s + a];
+    }
+    num = {wave_sum(num.x), wave_sum(num.y)};
+    den = {wave_sum(den.x), wave_sum(den.y)};
     if (threadIdx.x == 0) {
-        c64 num = {0.0, 0.0}, den = {0.0, 0.0};
-        for (int a = 0; a < s; ++a)
-            for (int b = 0; b < s; ++b) {
-                num = num + G1[a * s + b] * K[b * s + a];
-                den = den + G2[a * s + b] * K[b * s + a];
-            }
         if (bad_den(den)) {
             set_bd(c);
         } else {

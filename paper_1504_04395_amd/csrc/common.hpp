@@ -165,18 +165,30 @@ __device__ inline void block_reduce_store(c64 (&v)[K], c64* out) {
 
 // In a single workgroup (any size that is a multiple of 64, at most 256): sum K
 // values over `np` per-block partials laid out [block][K]; result in res[0..K)
-// (shared memory), visible after return.  Fixed order: strided per thread,
-// butterfly within each wave, waves in order.
+// (shared memory), visible after return.  Fixed order: strided per thread over
+// four accumulators, butterfly within each wave, waves in order.
 template <int K>
 __device__ inline void sum_partials(const c64* __restrict__ part, int np, c64* res) {
     __shared__ c64 sm[kWaves][K];
-    c64 v[K];
+    c64 v[K], acc[4][K];   // four independent accumulators keep four loads in flight
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = {0.0, 0.0};
-    for (int b = threadIdx.x; b < np; b += blockDim.x) {
+    for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int k = 0; k < K; ++k) v[k] = v[k] + part[(size_t)b * K + k];
+        for (int k = 0; k < K; ++k) acc[u][k] = {0.0, 0.0};
+    const int st = blockDim.x;
+    int b = threadIdx.x;
+    for (; b + 3 * st < np; b += 4 * st) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int k = 0; k < K; ++k) acc[u][k] = acc[u][k] + part[(size_t)(b + u * st) * K + k];
     }
+    for (; b < np; b += st) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc[0][k] = acc[0][k] + part[(size_t)b * K + k];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = (acc[0][k] + acc[1][k]) + (acc[2][k] + acc[3][k]);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int nw = (blockDim.x + 63) >> 6;
 #pragma unroll

@@ -64,7 +64,7 @@ struct Env {
     int n = 0, s = 0;
     int nb = 0;              // workgroups per streaming kernel (multiple of 8)
     int rpc = 0;             // rows per workgroup chunk
-    int p2 = 16;             // stage-2 partial count
+    int p2 = 1;              // partials left after the second reduction stage
     Flat fl{};               // n*s elements
     Layout ly{};             // row layout of the global family (L = min(2^ceil(log2 s), 16))
     Layout lyv{};            // vector layout (s = 1, L = 1)
@@ -126,6 +126,14 @@ void spmm_j(Env<T>& e, const Operand<T>& op, const Layout& ly, const T* X, T* Y,
 }
 template <class T, class Epi>
 void spmm(Env<T>& e, const Operand<T>& op, const Layout& ly, const T* X, T* Y, Epi epi, const Ctl* ctl) {
+    if constexpr (std::is_same<Epi, EpiNone>::value) {
+        if (ly.s == 1 && !op.sell) {   // single vector: 8 lanes per row
+            const int per_xcd = ((e.n + 7) / 8 + 31) / 32 * 32;
+            k_spmv_csr<T><<<e.nb, kBlock, 0, e.st>>>(ctl, op.csr, per_xcd, X, Y);
+            SKR_LAUNCHED();
+            return;
+        }
+    }
     // J of the SELL kernel follows ly; the CSR kernel always uses 16 lanes, J16 = ceil(s/16)
     const int J = (ly.s + ly.L - 1) / ly.L;
     const bool j16 = ly.s > 16;
@@ -139,8 +147,7 @@ Layout tile_layout(const Env<T>& e) { return Layout{e.s, 16, 4}; }
 
 template <class T>
 void reduce2(Env<T>& e, int E, int cond_slot = -1) {
-    dim3 g((E + kBlock - 1) / kBlock, e.p2);
-    k_reduce_parts<<<g, kBlock, 0, e.st>>>(e.ctl, cond_slot, e.part, e.nb, E, e.part2);
+    k_reduce_parts<<<(E + kWaves - 1) / kWaves, kBlock, 0, e.st>>>(e.ctl, cond_slot, e.part, e.nb, E, e.part2);
     SKR_LAUNCHED();
 }
 
@@ -155,6 +162,21 @@ inline size_t mat_lds(int s, int nmat, int ntile) {
     return (need > gram ? need : gram) * sizeof(c64);
 }
 
+// One CholeskyQR triangular pass (k_bl_tri arguments); real s <= 16 blocks use
+// the MFMA tile kernel.
+template <class T, int J>
+void tri_pass(Env<T>& e, int slot, int cond, int nchain, int add_shift, int mode, const T* Z, T* Out,
+              const T* Other) {
+    if constexpr (!Tr<T>::cplx && J == 1) {
+        k_bl_tri16<T><<<e.nb, kBlock, 0, e.st>>>(e.ctl, slot, cond, nchain, add_shift, e.tl, mode, e.mats, Z, Out,
+                                                Other, e.part);
+    } else {
+        k_bl_tri<T, J><<<e.nb, kBlock, mat_lds(e.s, 3, 1), e.st>>>(e.ctl, slot, cond, nchain, add_shift, e.tl, mode,
+                                                                    e.mats, Z, Out, Other, e.part);
+    }
+    SKR_LAUNCHED();
+}
+
 // CholeskyQR2 (+ shifted first pass) of Z into Q; the Gram Z^H Z partials must
 // already be in e.part.  R factor in mats (slot 0: M_S, slot 1: M_T).
 // mode/Other: Gram fused into the final pass (TRI_* flags).
@@ -163,27 +185,52 @@ void cholqr(Env<T>& e, int slot, const T* Z, T* Q, int mode, const T* Other) {
     const int s = e.s, ss = s * s;
     const double u = sizeof(typename Tr<T>::R) == 4 ? 0x1p-24 : 0x1p-53;   // stored precision
     size_t lds4 = 4 * (size_t)ss * sizeof(c64);
-    size_t ldsT = mat_lds(s, 3, 1);
     reduce2(e, ss);
     k_qr_chol<<<1, kScalar, lds4, e.st>>>(e.ctl, slot, 1, e.n, s, e.part2, e.p2, e.mats, u);
     SKR_LAUNCHED();
     // Gram of Q1 = Z S1^{-1}
-    k_bl_tri<T, J><<<e.nb, kBlock, ldsT, e.st>>>(e.ctl, slot, 0, 1, 0, e.tl, TRI_G_OUT_OUT, e.mats, Z, nullptr,
-                                                 nullptr, e.part);
-    SKR_LAUNCHED();
+    tri_pass<T, J>(e, slot, 0, 1, 0, TRI_G_OUT_OUT, Z, nullptr, nullptr);
     reduce2(e, ss);
     k_qr_chol<<<1, kScalar, lds4, e.st>>>(e.ctl, slot, 2, e.n, s, e.part2, e.p2, e.mats, u);
     SKR_LAUNCHED();
     // shifted case only: Gram of Q2 = Z S1^{-1} S2^{-1}
-    k_bl_tri<T, J><<<e.nb, kBlock, ldsT, e.st>>>(e.ctl, slot, 1, 2, 0, e.tl, TRI_G_OUT_OUT, e.mats, Z, nullptr,
-                                                 nullptr, e.part);
-    SKR_LAUNCHED();
+    tri_pass<T, J>(e, slot, 1, 2, 0, TRI_G_OUT_OUT, Z, nullptr, nullptr);
     reduce2(e, ss, slot);
     k_qr_chol<<<1, kScalar, lds4, e.st>>>(e.ctl, slot, 3, e.n, s, e.part2, e.p2, e.mats, u);
     SKR_LAUNCHED();
     // Q = Z S1^{-1} S2^{-1} [S3^{-1}]
-    k_bl_tri<T, J><<<e.nb, kBlock, ldsT, e.st>>>(e.ctl, slot, 0, 2, 1, e.tl, mode | TRI_WRITE, e.mats, Z, Q, Other,
-                                                 e.part);
+    tri_pass<T, J>(e, slot, 0, 2, 1, mode | TRI_WRITE, Z, Q, Other);
+}
+
+// Block update launchers: real s <= 16 blocks use the MFMA tile kernels.
+template <class T, int J, bool GRAM>
+void axpm(Env<T>& e, int mslot, int gslot, const T* A, const T* B, const T* C, T* Out) {
+    if constexpr (!Tr<T>::cplx && J == 1) {
+        k_bl_axpm16<T, GRAM><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.tl, e.mats, mslot, e.sc, gslot, A, B, C, Out,
+                                                        e.part);
+    } else {
+        k_bl_axpm<T, J, GRAM><<<e.nb, kBlock, mat_lds(e.s, 1, 1), e.st>>>(e.ctl, e.tl, e.mats, mslot, e.sc, gslot,
+                                                                           A, B, C, Out, e.part);
+    }
+    SKR_LAUNCHED();
+}
+template <class T, int J>
+void blrq_updz(Env<T>& e, T* X, const T* V, const T* Q, const T* W, T* Z) {
+    if constexpr (!Tr<T>::cplx && J == 1) {
+        k_blrq_updz16<T><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.tl, e.mats, X, V, Q, W, Z, e.part);
+    } else {
+        k_blrq_updz<T, J><<<e.nb, kBlock, mat_lds(e.s, 2, 2), e.st>>>(e.ctl, e.tl, e.mats, X, V, Q, W, Z, e.part);
+    }
+    SKR_LAUNCHED();
+}
+template <class T, int J>
+void blst_upd(Env<T>& e, T* X, const T* U, const T* St, const T* Tt, T* Z) {
+    if constexpr (!Tr<T>::cplx && J == 1) {
+        k_blst_upd16<T><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.tl, e.mats, e.sc, X, U, St, Tt, Z, e.part);
+    } else {
+        k_blst_upd<T, J><<<e.nb, kBlock, mat_lds(e.s, 2, 2), e.st>>>(e.ctl, e.tl, e.mats, e.sc, X, U, St, Tt, Z,
+                                                                    e.part);
+    }
     SKR_LAUNCHED();
 }
 
@@ -403,20 +450,14 @@ Method<T> make_bl_bicg_rq(Env<T>& e, Arena& ar, T* rhs, T* x) {
         spmm_j<T, J>(e, e.AH, lt, Vh, Wh, EpiNone{}, e.ctl);                      // W^ = A^H V^
         reduce2(e, ss);
         k_blrq_alpha<<<1, kScalar, 4 * (size_t)ss * sizeof(c64), e.st>>>(e.ctl, s, e.part2, e.p2, e.mats, e.sc);
-        k_blrq_updz<T, J><<<e.nb, kBlock, mat_lds(s, 2, 2), e.st>>>(e.ctl, e.tl, e.mats, x, V, Q, W, Z, e.part);
-        SKR_LAUNCHED();
+        blrq_updz<T, J>(e, x, V, Q, W, Z);
         cholqr<T, J>(e, 0, Z, Q, 0, nullptr);                                     // Q' S = Q - W alpha
-        k_bl_axpm<T, J, true><<<e.nb, kBlock, mat_lds(s, 1, 1), e.st>>>(e.ctl, e.tl, e.mats, M_ALPHAH, e.sc, 0,
-                                                                       Qh, Wh, nullptr, Zh, e.part);
-        SKR_LAUNCHED();
+        axpm<T, J, true>(e, M_ALPHAH, 0, Qh, Wh, nullptr, Zh);
         cholqr<T, J>(e, 1, Zh, Qh, TRI_G_OUT_OTHER, Q);                           // Q^' S^, M' = Q^'^H Q'
         reduce2(e, ss);
         k_blrq_beta<<<1, kScalar, 4 * (size_t)ss * sizeof(c64), e.st>>>(e.ctl, e.hist, s, e.part2, e.p2, e.mats);
-        k_bl_axpm<T, J, false><<<e.nb, kBlock, mat_lds(s, 1, 1), e.st>>>(e.ctl, e.tl, e.mats, M_BETA, e.sc, 0,
-                                                                        Q, V, nullptr, V, e.part);
-        k_bl_axpm<T, J, false><<<e.nb, kBlock, mat_lds(s, 1, 1), e.st>>>(e.ctl, e.tl, e.mats, M_BETAH, e.sc, 0,
-                                                                        Qh, Vh, nullptr, Vh, e.part);
-        SKR_LAUNCHED();
+        axpm<T, J, false>(e, M_BETA, 0, Q, V, nullptr, V);
+        axpm<T, J, false>(e, M_BETAH, 0, Qh, Vh, nullptr, Vh);
     };
     return m;
 }
@@ -450,21 +491,15 @@ Method<T> make_bl_bicgstab_rq(Env<T>& e, Arena& ar, T* rhs, T* x) {
         spmm_j<T, J>(e, e.A, lt, U, W, EpiGram<T, J>{Rt, e.part}, e.ctl);           // W = A U, G = R~^H W
         reduce2(e, ss);
         k_blst_a<<<1, kScalar, 4 * (size_t)ss * sizeof(c64), e.st>>>(e.ctl, s, e.part2, e.p2, e.mats, e.sc);
-        k_bl_axpm<T, J, false><<<e.nb, kBlock, mat_lds(s, 1, 1), e.st>>>(e.ctl, e.tl, e.mats, M_TMP, e.sc, 0,
-                                                                        Q, W, nullptr, St, e.part);  // S~ = Q - W a
-        SKR_LAUNCHED();
+        axpm<T, J, false>(e, M_TMP, 0, Q, W, nullptr, St);                         // S~ = Q - W a
         spmm_j<T, J>(e, e.A, lt, St, Tt, EpiGramOmega<T, J>{St, e.part}, e.ctl);    // T~ = A S~
         reduce2(e, 2 * ss);
         k_blst_omega<<<1, kScalar, 4 * (size_t)ss * sizeof(c64), e.st>>>(e.ctl, s, e.part2, e.p2, e.mats, e.sc);
-        k_blst_upd<T, J><<<e.nb, kBlock, mat_lds(s, 2, 2), e.st>>>(e.ctl, e.tl, e.mats, e.sc, x, U, St, Tt, Z,
-                                                                  e.part);
-        SKR_LAUNCHED();
+        blst_upd<T, J>(e, x, U, St, Tt, Z);
         cholqr<T, J>(e, 0, Z, Q, TRI_G_OTHER_OUT, Rt);                            // Q' Sigma = Z, N' = R~^H Q'
         reduce2(e, ss);
         k_blst_b<<<1, kScalar, 4 * (size_t)ss * sizeof(c64), e.st>>>(e.ctl, e.hist, s, e.part2, e.p2, e.mats, e.sc);
-        k_bl_axpm<T, J, false><<<e.nb, kBlock, mat_lds(s, 1, 1), e.st>>>(e.ctl, e.tl, e.mats, M_B, e.sc,
-                                                                        SC_GAMMA, Q, U, W, U, e.part);
-        SKR_LAUNCHED();
+        axpm<T, J, false>(e, M_B, SC_GAMMA, Q, U, W, U);                           // U = Q + (U - omega W) b
     };
     return m;
 }

@@ -3,7 +3,10 @@
 // pivot breakdown test, solves with G and with G^H, upper Cholesky factors
 // (G = S^H S), triangular inverses and small products.  Matrices are row-major
 // complex doubles; real problems carry zero imaginary parts, which every routine
-// here keeps exactly zero.  All routines are called by the whole workgroup.
+// here keeps exactly zero.  All routines are called by the whole workgroup, which
+// is one wavefront (64 threads): reductions across it use lane shuffles, and
+// the steps of a factorisation or substitution are parallel over the matrix
+// entries they update, with a barrier between steps.
 #pragma once
 
 #include "common.hpp"
@@ -41,121 +44,144 @@ __device__ inline void sm_gemm(c64* C, const c64* A, int ta, const c64* B, int t
     __syncthreads();
 }
 
-__device__ inline double sm_frob2(const c64* A, int count, double* red /* shared, >= 1 */) {
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int e = 0; e < count; ++e) t += abs2(A[e]);
-        *red = t;
-    }
-    __syncthreads();
-    double r = *red;
-    __syncthreads();
-    return r;
+__device__ inline double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+__device__ inline int wave_all(int ok) { return __all(ok); }
+
+// ||A||_F^2 over `count` entries (fixed order: strided per lane, butterfly).
+__device__ inline double sm_frob2(const c64* A, int count, double* red /* unused */) {
+    (void)red;
+    double t = 0.0;
+    for (int e = threadIdx.x; e < count; e += blockDim.x) t += abs2(A[e]);
+    return wave_sum(t);
 }
 
 // In-place LU with partial pivoting, P G = L U (unit L below the diagonal, U on
-// and above).  piv[k] = row swapped with k at step k.  Returns 1 if U passes the
-// pivot test |u_kk| > s * 2^-52 * max |u_ij| with all entries finite, else 0.
-__device__ inline int sm_lu(c64* A, int* piv, int s, int* flag /* shared */) {
+// and above).  piv[k] = row swapped with k at step k: the first row of largest
+// |re| + |im| in column k (LAPACK's choice).  Returns 1 if U passes the pivot
+// test |u_kk| > s * 2^-52 * max |u_ij| with all entries finite, else 0.
+__device__ inline int sm_lu(c64* A, int* piv, int s, int* flag) {
+    (void)flag;
+    const int t = threadIdx.x;
     for (int k = 0; k < s; ++k) {
-        if (threadIdx.x == 0) {
-            int p = k;
-            double best = cabs1(A[k * s + k]);
-            for (int i = k + 1; i < s; ++i) {
-                double v = cabs1(A[i * s + k]);
-                if (v > best) { best = v; p = i; }
-            }
-            piv[k] = p;
+        double v = -1.0;
+        int idx = k;
+        if (t >= k && t < s) {
+            v = cabs1(A[t * s + k]);
+            idx = t;
         }
-        __syncthreads();
-        const int p = piv[k];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double v2 = __shfl_xor(v, off, 64);
+            const int i2 = __shfl_xor(idx, off, 64);
+            if (v2 > v || (v2 == v && i2 < idx)) {
+                v = v2;
+                idx = i2;
+            }
+        }
+        const int p = idx;
+        if (t == 0) piv[k] = p;
         if (p != k) {
-            for (int j = threadIdx.x; j < s; j += blockDim.x) {
-                c64 t = A[k * s + j];
+            for (int j = t; j < s; j += blockDim.x) {
+                c64 x = A[k * s + j];
                 A[k * s + j] = A[p * s + j];
-                A[p * s + j] = t;
+                A[p * s + j] = x;
             }
             __syncthreads();
         }
         const c64 d = A[k * s + k];
-        for (int i = k + 1 + threadIdx.x; i < s; i += blockDim.x) A[i * s + k] = cdiv(A[i * s + k], d);
+        for (int i = k + 1 + t; i < s; i += blockDim.x) A[i * s + k] = cdiv(A[i * s + k], d);
         __syncthreads();
         const int m = s - k - 1;
-        for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
-            int i = k + 1 + e / m, j = k + 1 + e % m;
+        for (int e = t; e < m * m; e += blockDim.x) {
+            const int i = k + 1 + e / m, j = k + 1 + e % m;
             A[i * s + j] = A[i * s + j] - A[i * s + k] * A[k * s + j];
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        double umax = 0.0;
-        int ok = 1;
-        for (int i = 0; i < s; ++i)
-            for (int j = i; j < s; ++j) {
-                c64 u = A[i * s + j];
-                if (!cfinite(u)) ok = 0;
-                umax = fmax(umax, cabs(u));
-            }
-        if (!(umax > 0.0)) ok = 0;
-        for (int k = 0; k < s && ok; ++k)
-            if (!(cabs(A[k * s + k]) > s * 0x1p-52 * umax)) ok = 0;
-        for (int i = 0; i < s; ++i)
-            for (int j = 0; j < s; ++j)
-                if (!cfinite(A[i * s + j])) ok = 0;
-        *flag = ok;
+    double umax = 0.0;
+    int fin = 1;
+    for (int e = t; e < s * s; e += blockDim.x) {
+        const int i = e / s, j = e - i * s;
+        const c64 u = A[e];
+        if (!cfinite(u)) fin = 0;
+        if (j >= i) umax = fmax(umax, cabs(u));
     }
-    __syncthreads();
-    int ok = *flag;
-    __syncthreads();
-    return ok;
+    umax = wave_max(umax);
+    int ok = fin && umax > 0.0;
+    for (int k = t; k < s; k += blockDim.x)
+        if (!(cabs(A[k * s + k]) > s * 0x1p-52 * umax)) ok = 0;
+    return wave_all(ok);
 }
 
 // B := G^{-1} B for B s x m (row-major, leading dimension m), G = P^T L U.
-// Columns of B are independent: thread j solves column j (no barriers inside).
+// Row swaps column by column, then forward and back substitution, each step
+// parallel over the entries it updates.
 __device__ inline void sm_lu_solve(const c64* LU, const int* piv, c64* B, int s, int m) {
-    for (int j = threadIdx.x; j < m; j += blockDim.x) {
+    const int t = threadIdx.x;
+    for (int j = t; j < m; j += blockDim.x)
         for (int k = 0; k < s; ++k) {
-            int p = piv[k];
+            const int p = piv[k];
             if (p != k) {
-                c64 t = B[k * m + j];
+                c64 x = B[k * m + j];
                 B[k * m + j] = B[p * m + j];
-                B[p * m + j] = t;
+                B[p * m + j] = x;
             }
         }
-        for (int k = 0; k < s; ++k) {  // unit lower
-            const c64 bk = B[k * m + j];
-            for (int i = k + 1; i < s; ++i) B[i * m + j] = B[i * m + j] - LU[i * s + k] * bk;
-        }
-        for (int k = s - 1; k >= 0; --k) {  // upper
-            const c64 bk = cdiv(B[k * m + j], LU[k * s + k]);
-            B[k * m + j] = bk;
-            for (int i = 0; i < k; ++i) B[i * m + j] = B[i * m + j] - LU[i * s + k] * bk;
-        }
-    }
     __syncthreads();
+    for (int k = 0; k + 1 < s; ++k) {   // unit lower
+        const int n1 = (s - k - 1) * m;
+        for (int e = t; e < n1; e += blockDim.x) {
+            const int i = k + 1 + e / m, j = e % m;
+            B[i * m + j] = B[i * m + j] - LU[i * s + k] * B[k * m + j];
+        }
+        __syncthreads();
+    }
+    for (int k = s - 1; k >= 0; --k) {  // upper
+        for (int j = t; j < m; j += blockDim.x) B[k * m + j] = cdiv(B[k * m + j], LU[k * s + k]);
+        __syncthreads();
+        const int n1 = k * m;
+        for (int e = t; e < n1; e += blockDim.x) {
+            const int i = e / m, j = e % m;
+            B[i * m + j] = B[i * m + j] - LU[i * s + k] * B[k * m + j];
+        }
+        __syncthreads();
+    }
 }
 
-// B := G^{-H} B, with G = P^T L U, i.e. solve U^H L^H P X = B (column-parallel).
+// B := G^{-H} B, with G = P^T L U, i.e. solve U^H L^H P X = B.
 __device__ inline void sm_lu_solve_h(const c64* LU, const int* piv, c64* B, int s, int m) {
-    for (int j = threadIdx.x; j < m; j += blockDim.x) {
-        for (int k = 0; k < s; ++k) {  // U^H (lower, diagonal conj(u_kk))
-            const c64 bk = cdiv(B[k * m + j], conj_(LU[k * s + k]));
-            B[k * m + j] = bk;
-            for (int i = k + 1; i < s; ++i) B[i * m + j] = B[i * m + j] - conj_(LU[k * s + i]) * bk;
+    const int t = threadIdx.x;
+    for (int k = 0; k < s; ++k) {       // U^H: lower, diagonal conj(u_kk)
+        for (int j = t; j < m; j += blockDim.x) B[k * m + j] = cdiv(B[k * m + j], conj_(LU[k * s + k]));
+        __syncthreads();
+        const int n1 = (s - k - 1) * m;
+        for (int e = t; e < n1; e += blockDim.x) {
+            const int i = k + 1 + e / m, j = e % m;
+            B[i * m + j] = B[i * m + j] - conj_(LU[k * s + i]) * B[k * m + j];
         }
-        for (int k = s - 1; k >= 0; --k) {  // L^H (unit upper)
-            const c64 bk = B[k * m + j];
-            for (int i = 0; i < k; ++i) B[i * m + j] = B[i * m + j] - conj_(LU[k * s + i]) * bk;
+        __syncthreads();
+    }
+    for (int k = s - 1; k > 0; --k) {   // L^H: unit upper
+        const int n1 = k * m;
+        for (int e = t; e < n1; e += blockDim.x) {
+            const int i = e / m, j = e % m;
+            B[i * m + j] = B[i * m + j] - conj_(LU[k * s + i]) * B[k * m + j];
         }
-        for (int k = s - 1; k >= 0; --k) {  // X = P^T W
-            int p = piv[k];
+        __syncthreads();
+    }
+    for (int j = t; j < m; j += blockDim.x)   // X = P^T W
+        for (int k = s - 1; k >= 0; --k) {
+            const int p = piv[k];
             if (p != k) {
-                c64 t = B[k * m + j];
+                c64 x = B[k * m + j];
                 B[k * m + j] = B[p * m + j];
-                B[p * m + j] = t;
+                B[p * m + j] = x;
             }
         }
-    }
     __syncthreads();
 }
 

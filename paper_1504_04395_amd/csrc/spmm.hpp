@@ -284,6 +284,37 @@ __global__ __launch_bounds__(kBlock) void k_spmm_csr(const Ctl* ctl, CsrOp<T> A,
     epi_finish<Epi, J>(epi, st, blockIdx.x, s);
 }
 
+// Single vector (s = 1): y = A x with 8 lanes per row.  Lane e of a row's group
+// takes entries k0 + e, k0 + e + 8, ... and the 8 partial sums are added by a
+// butterfly inside the group.  Same per-XCD row sweep as k_spmm_csr.
+__device__ inline double shfl_xor_v(double v, int off) { return __shfl_xor(v, off, 64); }
+__device__ inline float shfl_xor_v(float v, int off) { return __shfl_xor(v, off, 64); }
+__device__ inline c64 shfl_xor_v(c64 v, int off) { return {__shfl_xor(v.x, off, 64), __shfl_xor(v.y, off, 64)}; }
+__device__ inline c32 shfl_xor_v(c32 v, int off) { return {__shfl_xor(v.x, off, 64), __shfl_xor(v.y, off, 64)}; }
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_spmv_csr(const Ctl* ctl, CsrOp<T> A, int rows_per_xcd,
+                                                      const T* __restrict__ x, T* __restrict__ y) {
+    if (stopped(ctl)) return;
+    const int sub = threadIdx.x & 7;
+    const int grp = threadIdx.x >> 3;                     // 32 rows per workgroup pass
+    const int xcd = blockIdx.x & 7, q = blockIdx.x >> 3, nq = gridDim.x >> 3;
+    const int r0 = xcd * rows_per_xcd;
+    const int r1 = min(A.n, r0 + rows_per_xcd);
+    for (int base = r0 + q * 32; base < r1; base += nq * 32) {
+        const int i = base + grp;
+        const bool valid = i < r1;                         // uniform inside the 8-lane group
+        const int k0 = valid ? A.rp[i] : 0;
+        const int k1 = valid ? A.rp[i + 1] : 0;
+        T acc = zero<T>();
+        for (int k = k0 + sub; k < k1; k += 8) acc = fma_(A.va[k], x[A.ci[k]], acc);
+        acc = acc + shfl_xor_v(acc, 4);
+        acc = acc + shfl_xor_v(acc, 2);
+        acc = acc + shfl_xor_v(acc, 1);
+        if (valid && sub == 0) y[i] = acc;
+    }
+}
+
 template <class T, int J, class Epi>
 __global__ __launch_bounds__(kBlock) void k_spmm_sell(const Ctl* ctl, SellOp<T> A, Layout ly, int chunks_per_block,
                                                        const T* __restrict__ X, T* __restrict__ Y, Epi epi) {
