@@ -78,7 +78,7 @@ def spmm_roofline(pkg, ctx, A, n, nnz, s, stream, reps=50):
     ms = e0.elapsed_time(e1) / reps
     bytes_alg = nnz * (8 + 4) + 4 * (n + 1) + 2 * n * s * 8
     gbs = bytes_alg / (ms * 1e-3) / 1e9
-    kernel = "k_spmm_csr<double,1,EpiNone>"
+    kernel = "k_spmm_csr8<double,EpiNone>"
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": counter_traffic(kernel),
             "kernel": kernel, "avg_us": round(ms * 1e3, 2), "bytes_per_launch": bytes_alg}
@@ -205,6 +205,7 @@ def main():
                 dt = time.perf_counter() - tm
                 t_mixed += dt
                 mixed[m] = {"status": info.status_name, "outer": info.outer_iterations,
+                            "outer_redone_in_fp64": info.fp64_outer_iterations,
                             "inner_iterations": info.iterations, "rel_res_true": info.rel_res_true,
                             "s_per_solve": round(dt, 4), "rhs_per_s": round(s / dt, 3)}
         log("mixed step: " + ", ".join(f"{m} {mixed[m]['status']} outer={mixed[m]['outer']}" for m in METHODS))

@@ -109,6 +109,10 @@ typedef struct {
     double* history;
     int32_t history_cap;
     int32_t history_len;
+    int32_t fp64_outer_iterations; /* FP32 path: refinement steps run in FP64
+                                    * because the FP32 QR or inner solve failed
+                                    * (breakdown, divergence) or an earlier FP32
+                                    * step did not halve the true residual     */
 } skr_result;
 
 /* Fill *opts with the defaults listed above. */

@@ -130,6 +130,7 @@ struct Ctl {
     double tol;
     double nr0;         // ||R_0||_F
     double res;         // latest recursive ||R_k||_F
+    double div_limit;   // > 0: stop as diverged once ||R_k|| > div_limit * ||R_0|| (inner solves)
 };
 
 enum { ST_OK = 0, ST_RUNNING = 1, ST_BREAKDOWN = 2 };

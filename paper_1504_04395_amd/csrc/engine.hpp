@@ -115,6 +115,12 @@ void spmm_j(Env<T>& e, const Operand<T>& op, const Layout& ly, const T* X, T* Y,
         int nchunks = (e.n + op.sl.C - 1) / op.sl.C;
         int cpb = (nchunks + e.nb - 1) / e.nb;
         k_spmm_sell<T, J, Epi><<<e.nb, kBlock, 0, e.st>>>(ctl, op.sl, ly, cpb, X, Y, epi);
+    } else if (!Tr<T>::cplx && J16 == 1 && ly.s % 2 == 0) {
+        if constexpr (!Tr<T>::cplx && J16 == 1) {
+            // real, even s <= 16: 8 lanes per row, two columns per lane
+            const int per_xcd = ((e.n + 7) / 8 + 63) / 64 * 64;
+            k_spmm_csr8<T, Epi><<<e.nb, kBlock, 0, e.st>>>(ctl, op.csr, ly, per_xcd, X, Y, epi);
+        }
     } else {
         // CSR kernel: 16 lanes per row whatever s is (its lane layout is the DPP row)
         const Layout l16{ly.s, 16, 4};

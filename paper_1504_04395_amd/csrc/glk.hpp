@@ -71,6 +71,10 @@ __device__ inline bool end_of_iteration(Ctl* c, double* hist, double res2) {
         set_breakdown(c);
         return false;
     }
+    if (c->div_limit > 0.0 && res > c->div_limit * c->nr0) {   // inner solves only
+        set_breakdown(c);
+        return false;
+    }
     if (c->iter >= c->maxit) {
         c->status = ST_RUNNING;
         c->done = 1;

@@ -415,7 +415,7 @@ struct InnerStats {
 // Run a method to completion on A D = rhs (the caller enqueued rhs).
 template <class T>
 InnerStats iterate(skr_context* c, Env<T>& e, Method<T>& m, int method, double tol, int maxit, int every,
-                   bool use_graph, uint64_t key_extra) {
+                   bool use_graph, uint64_t key_extra, double div_limit = 0.0) {
     Ctl* h = c->hin;
     std::memset(h, 0, sizeof(Ctl));
     h->done = 0;
@@ -423,6 +423,7 @@ InnerStats iterate(skr_context* c, Env<T>& e, Method<T>& m, int method, double t
     h->bd_iter = -1;
     h->maxit = maxit;
     h->tol = tol;
+    h->div_limit = div_limit;
     SKR_HIP(hipMemcpyAsync(e.ctl, h, sizeof(Ctl), hipMemcpyHostToDevice, e.st));
     m.init();
     if (every < 1) every = 1;
@@ -578,6 +579,7 @@ int solve_fp64(skr_context* c, const skr_matrix* M, int s, const T* B, T* X, boo
     res->iterations = st.iters;
     res->matvecs = st.matvecs;
     res->outer_iterations = 0;
+    res->fp64_outer_iterations = 0;
     res->breakdown_iter = st.bd_iter;
     res->rel_res_recursive = st.rres;
     res->rel_res_true = rel;
@@ -607,33 +609,41 @@ int solve_mixed(skr_context* c, skr_matrix* M, int s, const T* B, T* X, bool x0z
     f.st = c->stream();
     f.A = operand<L>(M, adjoint != 0, true);
     f.AH = operand<L>(M, adjoint == 0, true);
-    auto carve = [&](Arena& ar, T** tmp, L** r32, L** d32, Method<L>* m) {
-        take_common(e, ar, 4);
+    // FP32 method on (r32, d32); the same method in FP64 on (r64, d64) runs an
+    // outer step whose FP32 inner solve made no progress.
+    auto carve = [&](Arena& ar, T** tmp, L** r32, L** d32, Method<L>* m, T** r64, T** d64, Method<T>* m64) {
+        take_common(e, ar, o.maxit);
         take_common(f, ar, o.maxit);
         *tmp = (T*)ar.take(e.blk_bytes());
         *r32 = (L*)ar.take(f.blk_bytes());
         *d32 = (L*)ar.take(f.blk_bytes());
         *m = make_method<L, J>(method, f, ar, *r32, *d32);
+        *r64 = (T*)ar.take(e.blk_bytes());
+        *d64 = (T*)ar.take(e.blk_bytes());
+        *m64 = make_method<T, J>(method, e, ar, *r64, *d64);
     };
-    T* tmp;
+    T *tmp, *r64, *d64;
     L *r32, *d32;
     Method<L> m;
+    Method<T> m64;
     Arena sz;
-    carve(sz, &tmp, &r32, &d32, &m);
+    carve(sz, &tmp, &r32, &d32, &m, &r64, &d64, &m64);
     ensure_arena(c, sz.off);
     Arena ar;
     ar.base = c->arena;
     ar.cap = c->arena_cap;
-    carve(ar, &tmp, &r32, &d32, &m);
+    carve(ar, &tmp, &r32, &d32, &m, &r64, &d64, &m64);
 
     if (x0zero) {
         k_fill0<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, X, nullptr, nullptr, nullptr);
         SKR_LAUNCHED();
     }
     std::vector<double> hist;
-    int iters = 0, outer = 0, status = SKR_NOT_CONVERGED, bd = -1;
+    int iters = 0, outer = 0, status = SKR_NOT_CONVERGED, bd = -1, outer64 = 0;
     long long mv = 0;
-    double rel = 0.0, rres = 0.0;
+    double rel = 0.0, rres = 0.0, prev_rel = -1.0;
+    bool use64 = false;   // once an FP32 step fails to halve the true residual, stay in FP64
+    const bool pre = o.preprocess_qr != 0;
     for (;;) {
         spmm(e, e.A, e.ly, X, tmp, EpiNone{}, (const Ctl*)nullptr);
         k_resid<T, L><<<e.nb, kBlock, 0, e.st>>>(e.fl, B, tmp, (T*)nullptr, r32, e.part);
@@ -656,29 +666,48 @@ int solve_mixed(skr_context* c, skr_matrix* M, int s, const T* B, T* X, bool x0z
             status = SKR_NOT_CONVERGED;
             break;
         }
+        if (prev_rel > 0.0 && !(rel < 0.5 * prev_rel)) use64 = true;
+        prev_rel = rel;
         ++outer;
-        bool pre = o.preprocess_qr != 0;
-        if (pre && !preprocess<L, J>(c, f, r32)) {
-            status = SKR_BREAKDOWN;
-            bd = iters;
-            break;
-        }
         // inner target: inner_tol, relaxed on the last step to what is still
         // needed (half of tol / current relative residual), never above 0.5
         const double inner = std::max(o.inner_tol, std::min(0.5, 0.5 * o.tol / rel));
-        InnerStats st = iterate<L>(c, f, m, method, inner, o.maxit, o.check_every, o.use_graph != 0,
-                                   fnv(&ar, sizeof(ar), 1));
-        iters += st.iters;
-        mv += st.matvecs + s;  // + the outer residual product
-        rres = st.rres;
-        if (!(st.rres < 1.0) || !std::isfinite(st.rres)) {
-            // the inner solve made no progress (e.g. it diverged in FP32): keep
-            // the current X and stop
+        mv += s;  // the outer residual product
+        if (!use64 && (!pre || preprocess<L, J>(c, f, r32))) {
+            // an FP32 inner solve whose residual grows 1e4-fold is abandoned early
+            InnerStats st = iterate<L>(c, f, m, method, inner, o.maxit, o.check_every, o.use_graph != 0,
+                                       fnv(&ar, sizeof(ar), 1), 1e4);
+            iters += st.iters;
+            mv += st.matvecs;
+            rres = st.rres;
+            if (st.rres < 1.0 && std::isfinite(st.rres)) {
+                k_xupd<T, L, J><<<e.nb, kBlock, mat_lds(s, 1, 1), e.st>>>(e.tl, f.mats, pre ? M_RB : -1, X, d32, 0);
+                SKR_LAUNCHED();
+                continue;
+            }
+        }
+        // This step in FP64: the FP32 QR of the residual or the FP32 inner solve
+        // failed (X is unchanged and tmp still holds A X), or FP32 steps stopped
+        // paying off.
+        ++outer64;
+        k_resid<T, T><<<e.nb, kBlock, 0, e.st>>>(e.fl, B, tmp, r64, (T*)nullptr, e.part);
+        SKR_LAUNCHED();
+        if (pre && !preprocess<T, J>(c, e, r64)) {
             status = SKR_BREAKDOWN;
             bd = iters;
             break;
         }
-        k_xupd<T, L, J><<<e.nb, kBlock, mat_lds(s, 1, 1), e.st>>>(e.tl, f.mats, pre ? M_RB : -1, X, d32, 0);
+        InnerStats s64 = iterate<T>(c, e, m64, method, inner, o.maxit, o.check_every, o.use_graph != 0,
+                                    fnv(&ar, sizeof(ar), 2));
+        iters += s64.iters;
+        mv += s64.matvecs;
+        rres = s64.rres;
+        if (!(s64.rres < 1.0) || !std::isfinite(s64.rres)) {
+            status = SKR_BREAKDOWN;   // no progress in FP64 either: keep X and stop
+            bd = iters;
+            break;
+        }
+        k_xupd<T, T, J><<<e.nb, kBlock, mat_lds(s, 1, 1), e.st>>>(e.tl, e.mats, pre ? M_RB : -1, X, d64, 0);
         SKR_LAUNCHED();
     }
     res->status = status;
@@ -686,6 +715,7 @@ int solve_mixed(skr_context* c, skr_matrix* M, int s, const T* B, T* X, bool x0z
     res->iterations = iters;
     res->matvecs = mv;
     res->outer_iterations = outer;
+    res->fp64_outer_iterations = outer64;
     res->breakdown_iter = bd;
     res->rel_res_recursive = rres;
     res->rel_res_true = rel;

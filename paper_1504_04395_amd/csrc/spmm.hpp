@@ -284,6 +284,109 @@ __global__ __launch_bounds__(kBlock) void k_spmm_csr(const Ctl* ctl, CsrOp<T> A,
     epi_finish<Epi, J>(epi, st, blockIdx.x, s);
 }
 
+// Real blocks with even s <= 16: 8 lanes per row, lane l holding columns 2l and
+// 2l + 1 (one 16-byte load of X per nonzero for FP64).  A DPP row of 16 lanes
+// carries two matrix rows; the entries of both are loaded 8 at a time (lane u
+// of each half loads entry u) and broadcast inside their half.  A wave owns 16
+// consecutive rows per pass (two passes of 8).  The matrix stream (indices,
+// values) is read and Y is written with non-temporal hints, so that L2 keeps
+// the X rows that neighbouring matrix rows gather again.  Epilogues see the
+// tile-16 layout: the wave's 16 x 16 result tile goes through LDS and each
+// lane then holds column (lane % 16) of rows 4v + lane / 16.
+template <class T> struct Pair;
+template <> struct Pair<double> { using type = double2; };
+template <> struct Pair<float> { using type = float2; };
+
+template <class T, class Epi>
+__global__ __launch_bounds__(kBlock) void k_spmm_csr8(const Ctl* ctl, CsrOp<T> A, Layout ly, int rows_per_xcd,
+                                                       const T* __restrict__ X, T* __restrict__ Y, Epi epi) {
+    if (stopped(ctl)) return;
+    using P2 = typename Pair<T>::type;
+    constexpr int U = 8;
+    constexpr bool EPI = !std::is_same<Epi, EpiNone>::value;
+    const int s = ly.s;
+    const int lane = threadIdx.x & 15, half = lane >> 3, l8 = lane & 7;
+    const int w = threadIdx.x >> 6, g = (threadIdx.x >> 4) & 3;
+    const int xcd = blockIdx.x & 7, q = blockIdx.x >> 3, nq = gridDim.x >> 3;
+    const int r0 = xcd * rows_per_xcd;
+    const int r1 = min(A.n, r0 + rows_per_xcd);
+    const bool colok = 2 * l8 < s;          // s is even: both of the lane's columns exist, or neither
+    const int cofs = colok ? 2 * l8 : 0;
+    __shared__ T tiles[EPI ? kWaves : 1][EPI ? 16 * 17 : 1];
+    typename Epi::St st;
+    epi.init(st);
+    for (int base = r0 + q * 64; base < r1; base += nq * 64) {
+        const int wb = base + 16 * w;
+        int i[2], k0[2], k1[2];
+        bool valid[2];
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            i[p] = wb + 8 * p + 2 * g + half;
+            valid[p] = i[p] < r1;
+            k0[p] = valid[p] ? A.rp[i[p]] : 0;
+            k1[p] = valid[p] ? A.rp[i[p] + 1] : 0;
+        }
+        T ax[2] = {T(0), T(0)}, ay[2] = {T(0), T(0)};
+        for (int off = 0;; off += U) {
+            int mc[2];
+            T ma[2];
+            int more = 0;
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                const int k = k0[p] + off + l8;
+                const int kc = max(0, min(k, k1[p] - 1));   // clamped: always a valid entry
+                mc[p] = __builtin_nontemporal_load(&A.ci[kc]);
+                const T v = __builtin_nontemporal_load(&A.va[kc]);
+                ma[p] = k < k1[p] ? v : T(0);
+                more |= k0[p] + off + U < k1[p];
+            }
+            more = __any(more);
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                sfor<0, U>([&](auto ic) {
+                    constexpr int u = decltype(ic)::value;
+                    const int c0 = rbc32<u>(mc[p]), c1 = rbc32<u + 8>(mc[p]);
+                    const T a0 = rbc64<u>(ma[p]), a1 = rbc64<u + 8>(ma[p]);
+                    const int c = half ? c1 : c0;
+                    const T a = half ? a1 : a0;
+                    const P2 xv = *reinterpret_cast<const P2*>(X + (size_t)c * s + cofs);
+                    ax[p] = fma_(a, xv.x, ax[p]);
+                    ay[p] = fma_(a, xv.y, ay[p]);
+                });
+            }
+            if (!more) break;
+        }
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            if (valid[p] && colok) {
+                T* yr = Y + (size_t)i[p] * s + 2 * l8;
+                __builtin_nontemporal_store(ax[p], yr);
+                __builtin_nontemporal_store(ay[p], yr + 1);
+            }
+        }
+        if constexpr (EPI) {
+            T* tw = tiles[w];
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                const int lr = 8 * p + 2 * g + half;
+                tw[lr * 17 + 2 * l8] = colok ? ax[p] : T(0);
+                tw[lr * 17 + 2 * l8 + 1] = colok ? ay[p] : T(0);
+            }
+            __builtin_amdgcn_wave_barrier();
+            const int c = threadIdx.x & 15, qq = (threadIdx.x >> 4) & 3;
+            const Layout l16{s, 16, 4};
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int lr = 4 * v + qq;
+                const T y[1] = {tw[lr * 17 + c]};
+                epi.row(st, wb + lr, wb + lr < r1, c, l16, y);
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    epi_finish<Epi, 1>(epi, st, blockIdx.x, s);
+}
+
 // Single vector (s = 1): y = A x with 8 lanes per row.  Lane e of a row's group
 // takes entries k0 + e, k0 + e + 8, ... and the 8 partial sums are added by a
 // butterfly inside the group.  Same per-XCD row sweep as k_spmm_csr.

@@ -145,11 +145,11 @@ def test_wilson_full_bicgstab_rq(env):
     A.close()
 
 
-def test_block_fp32_inner_failure_is_reported(env, cfg2):
-    """On the full 3D problem the block method run in FP32 does not reach the
-    inner tolerance (its s x s systems are too ill-conditioned for FP32 data).
-    The refinement must then stop with BREAKDOWN and a finite X that is no worse
-    than X0 = 0, rather than apply a diverged correction."""
+def test_block_fp32_inner_failure_falls_back(env, cfg2):
+    """On the full 3D problem the block method's FP32 inner solve diverges (its
+    s x s coefficient systems reach condition numbers near 1e5, which FP32
+    block data cannot support).  The refinement stops that inner solve early,
+    redoes the step in FP64, reports how many steps it redid, and converges."""
     P, ctx = env
     import torch
     A = P.Matrix.from_csr(ctx, cfg2.A)
@@ -157,10 +157,8 @@ def test_block_fp32_inner_failure_is_reported(env, cfg2):
                       precision="fp32_refine", maxit=2000)
     A.close()
     X = X.cpu().numpy()
+    rel = np.linalg.norm(cfg2.B - cfg2.A.to_scipy() @ X) / np.linalg.norm(cfg2.B)
     say(f"  bl_bicgstab_rq fp32_refine: status={info.status_name} outer={info.outer_iterations} "
-        f"res={info.rel_res_true:.2e}")
-    assert np.all(np.isfinite(X))
-    if info.status != 0:
-        assert info.status_name == "breakdown" and info.rel_res_true <= 1.0
-    else:
-        assert info.rel_res_true < 1.5e-8
+        f"fp64 steps={info.fp64_outer_iterations} it={info.iterations} res={rel:.2e}")
+    assert info.status == 0 and rel < 1.5e-8
+    assert 0 <= info.fp64_outer_iterations <= info.outer_iterations

@@ -223,7 +223,8 @@ def test_mixed_precision_refinement(pkg, ctx, k, method):
     A = pkg.Matrix.from_csr(ctx, Acsr)
     X, info = pkg.solve(ctx, A, B, method, tol=1e-8, precision="fp32_refine", inner_tol=1e-4, max_outer=20)
     A.close()
-    say(f"  status={info.status_name} outer={info.outer_iterations} inner_it={info.iterations} "
+    say(f"  status={info.status_name} outer={info.outer_iterations} (fp64 {info.fp64_outer_iterations}) "
+        f"inner_it={info.iterations} "
         f"res={info.rel_res_true:.3e} err_vs_fp64_oracle={_rel(X, ref.X):.3e}")
     assert info.status == 0 and info.rel_res_true <= 1e-8
     assert _rel(X, ref.X) < 1e-6
