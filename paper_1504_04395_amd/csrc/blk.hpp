@@ -386,8 +386,10 @@ __device__ inline void tile_store(T* P, int b, int r1, int s, int c, int q, cons
     }
 }
 
-// k_bl_tri for real blocks with s <= 16 (same arguments and results).
-template <class T>
+// k_bl_tri for real blocks with s <= 16 (same arguments and results).  NC: the
+// most inverse factors this instance applies (1 or 3); OTH: whether the Gram's
+// second operand is another block (fewer live registers when it is not).
+template <class T, int NC, bool OTH>
 __global__ __launch_bounds__(kBlock) void k_bl_tri16(const Ctl* ctl, int slot, int cond, int nchain, int add_shift,
                                                      Tile16 tl, int mode, const c64* __restrict__ mats, const T* Z,
                                                      T* Out, const T* __restrict__ Other, c64* part) {
@@ -399,10 +401,12 @@ __global__ __launch_bounds__(kBlock) void k_bl_tri16(const Ctl* ctl, int slot, i
     const int base = slot == 0 ? M_S1 : M_T1;
     const int L = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int c = L & 15, q = L >> 4;
-    double m0[4], m1[4], m2[4];
+    double m0[4], m1[NC > 1 ? 4 : 1], m2[NC > 1 ? 4 : 1];
     mfma_bop(mats + (size_t)(base + 1) * ss, s, c, q, m0);
-    mfma_bop(mats + (size_t)(base + 3) * ss, s, c, q, m1);
-    mfma_bop(mats + (size_t)(base + 5) * ss, s, c, q, m2);
+    if constexpr (NC > 1) {
+        mfma_bop(mats + (size_t)(base + 3) * ss, s, c, q, m1);
+        mfma_bop(mats + (size_t)(base + 5) * ss, s, c, q, m2);
+    }
     __shared__ double tiles[kWaves][16 * kTileLd];
     __shared__ c64 glds[256];
     double* tw = tiles[w];
@@ -410,26 +414,43 @@ __global__ __launch_bounds__(kBlock) void k_bl_tri16(const Ctl* ctl, int slot, i
     g.clear();
     const int r0 = xcd_chunk(blockIdx.x, gridDim.x) * tl.rpc;
     const int r1 = min(tl.n, r0 + tl.rpc);
-    for (int b = r0 + 16 * w; b < r1; b += 16 * kWaves) {
-        double x[4];
-        tile_load<T>(Z, b, r1, s, c, q, x);
-        d4 o = mfma_apply(x, m0, tw, c, q);
-        if (nc > 1) {
-            double y[4] = {o[0], o[1], o[2], o[3]};
-            o = mfma_apply(y, m1, tw, c, q);
+    // software pipelining: the next tile's loads are issued before this tile's MFMAs
+    constexpr bool oth = OTH;
+    double xn[4], otn[4] = {0.0, 0.0, 0.0, 0.0};
+    int b = r0 + 16 * w;
+    if (b < r1) {
+        tile_load<T>(Z, b, r1, s, c, q, xn);
+        if (oth) tile_load<T>(Other, b, r1, s, c, q, otn);
+    }
+    for (; b < r1; b += 16 * kWaves) {
+        double x[4], ot[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            x[v] = xn[v];
+            ot[v] = otn[v];
         }
-        if (nc > 2) {
-            double y[4] = {o[0], o[1], o[2], o[3]};
-            o = mfma_apply(y, m2, tw, c, q);
+        const int bn = b + 16 * kWaves;
+        if (bn < r1) {
+            tile_load<T>(Z, bn, r1, s, c, q, xn);
+            if (oth) tile_load<T>(Other, bn, r1, s, c, q, otn);
+        }
+        d4 o = mfma_apply(x, m0, tw, c, q);
+        if constexpr (NC > 1) {
+            if (nc > 1) {
+                double y[4] = {o[0], o[1], o[2], o[3]};
+                o = mfma_apply(y, m1, tw, c, q);
+            }
+            if (nc > 2) {
+                double y[4] = {o[0], o[1], o[2], o[3]};
+                o = mfma_apply(y, m2, tw, c, q);
+            }
         }
         if (mode & TRI_WRITE) tile_store<T>(Out, b, r1, s, c, q, o);
         if (mode & (TRI_G_OUT_OUT | TRI_G_OTHER_OUT | TRI_G_OUT_OTHER)) {
-            double ot[4];
-            if (mode & (TRI_G_OTHER_OUT | TRI_G_OUT_OTHER)) tile_load<T>(Other, b, r1, s, c, q, ot);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const double ov[1] = {o[v]};
-                if (mode & TRI_G_OUT_OUT) {
+                if (!OTH) {
                     g.add(ov, ov);
                 } else {
                     const double tv[1] = {ot[v]};
@@ -464,9 +485,16 @@ __global__ __launch_bounds__(kBlock) void k_bl_axpm16(const Ctl* ctl, Tile16 tl,
     g.clear();
     const int r0 = xcd_chunk(blockIdx.x, gridDim.x) * tl.rpc;
     const int r1 = min(tl.n, r0 + tl.rpc);
-    for (int b = r0 + 16 * w; b < r1; b += 16 * kWaves) {
+    // software pipelining of the B stream (Out may alias B: a tile is loaded
+    // one iteration before it is written, and later tiles are never written early)
+    double xn[4];
+    int b = r0 + 16 * w;
+    if (b < r1) tile_load<T>(B, b, r1, s, c, q, xn);
+    for (; b < r1; b += 16 * kWaves) {
         double x[4], a[4] = {0.0, 0.0, 0.0, 0.0};
-        tile_load<T>(B, b, r1, s, c, q, x);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) x[v] = xn[v];
+        if (b + 16 * kWaves < r1) tile_load<T>(B, b + 16 * kWaves, r1, s, c, q, xn);
         if (Cm) {
             double y[4];
             tile_load<T>(Cm, b, r1, s, c, q, y);

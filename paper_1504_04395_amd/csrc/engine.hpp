@@ -174,8 +174,16 @@ template <class T, int J>
 void tri_pass(Env<T>& e, int slot, int cond, int nchain, int add_shift, int mode, const T* Z, T* Out,
               const T* Other) {
     if constexpr (!Tr<T>::cplx && J == 1) {
-        k_bl_tri16<T><<<e.nb, kBlock, 0, e.st>>>(e.ctl, slot, cond, nchain, add_shift, e.tl, mode, e.mats, Z, Out,
-                                                Other, e.part);
+        const bool oth = (mode & (TRI_G_OTHER_OUT | TRI_G_OUT_OTHER)) != 0;
+        if (nchain + add_shift <= 1 && !oth)
+            k_bl_tri16<T, 1, false><<<e.nb, kBlock, 0, e.st>>>(e.ctl, slot, cond, nchain, add_shift, e.tl, mode,
+                                                              e.mats, Z, Out, Other, e.part);
+        else if (!oth)
+            k_bl_tri16<T, 3, false><<<e.nb, kBlock, 0, e.st>>>(e.ctl, slot, cond, nchain, add_shift, e.tl, mode,
+                                                              e.mats, Z, Out, Other, e.part);
+        else
+            k_bl_tri16<T, 3, true><<<e.nb, kBlock, 0, e.st>>>(e.ctl, slot, cond, nchain, add_shift, e.tl, mode,
+                                                             e.mats, Z, Out, Other, e.part);
     } else {
         k_bl_tri<T, J><<<e.nb, kBlock, mat_lds(e.s, 3, 1), e.st>>>(e.ctl, slot, cond, nchain, add_shift, e.tl, mode,
                                                                     e.mats, Z, Out, Other, e.part);

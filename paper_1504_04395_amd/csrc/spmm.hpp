@@ -304,6 +304,8 @@ __global__ __launch_bounds__(kBlock) void k_spmm_csr8(const Ctl* ctl, CsrOp<T> A
     using P2 = typename Pair<T>::type;
     constexpr int U = 8;
     constexpr bool EPI = !std::is_same<Epi, EpiNone>::value;
+    constexpr bool G1 = std::is_same<Epi, EpiGram<T, 1>>::value;        // Z^H Y
+    constexpr bool G2 = std::is_same<Epi, EpiGramOmega<T, 1>>::value;   // (Y^H Z, Y^H Y)
     const int s = ly.s;
     const int lane = threadIdx.x & 15, half = lane >> 3, l8 = lane & 7;
     const int w = threadIdx.x >> 6, g = (threadIdx.x >> 4) & 3;
@@ -315,8 +317,19 @@ __global__ __launch_bounds__(kBlock) void k_spmm_csr8(const Ctl* ctl, CsrOp<T> A
     __shared__ T tiles[EPI ? kWaves : 1][EPI ? 16 * 17 : 1];
     typename Epi::St st;
     epi.init(st);
+    const int tc = threadIdx.x & 15, tq = (threadIdx.x >> 4) & 3;   // tile-16 layout of the epilogue
     for (int base = r0 + q * 64; base < r1; base += nq * 64) {
         const int wb = base + 16 * w;
+        double zp[4] = {0.0, 0.0, 0.0, 0.0};
+        if constexpr (G1 || G2) {   // the Gram's other operand, loaded before the product
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = wb + 4 * v + tq;
+                const bool ok = r < r1 && tc < s;
+                const double zz = (double)epi.Z[(size_t)(ok ? r : wb) * s + (ok ? tc : 0)];
+                zp[v] = ok ? zz : 0.0;
+            }
+        }
         int i[2], k0[2], k1[2];
         bool valid[2];
 #pragma unroll
@@ -373,13 +386,21 @@ __global__ __launch_bounds__(kBlock) void k_spmm_csr8(const Ctl* ctl, CsrOp<T> A
                 tw[lr * 17 + 2 * l8 + 1] = colok ? ay[p] : T(0);
             }
             __builtin_amdgcn_wave_barrier();
-            const int c = threadIdx.x & 15, qq = (threadIdx.x >> 4) & 3;
             const Layout l16{s, 16, 4};
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int lr = 4 * v + qq;
-                const T y[1] = {tw[lr * 17 + c]};
-                epi.row(st, wb + lr, wb + lr < r1, c, l16, y);
+                const int lr = 4 * v + tq;
+                if constexpr (G1) {
+                    const double zv[1] = {zp[v]}, yv[1] = {(double)tw[lr * 17 + tc]};
+                    st.g.add(zv, yv);
+                } else if constexpr (G2) {
+                    const double zv[1] = {zp[v]}, yv[1] = {(double)tw[lr * 17 + tc]};
+                    st.g1.add(yv, zv);
+                    st.g2.add(yv, yv);
+                } else {
+                    const T y[1] = {tw[lr * 17 + tc]};
+                    epi.row(st, wb + lr, wb + lr < r1, tc, l16, y);
+                }
             }
             __builtin_amdgcn_wave_barrier();
         }
