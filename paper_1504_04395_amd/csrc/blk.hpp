@@ -61,27 +61,6 @@ template <class T, int J> struct RowPasses { static constexpr int value = Tr<T>:
     const int r1_ = min((tl).n, r0_ + (tl).rpc);                                       \
     for (int base_ = r0_; base_ < r1_; base_ += 16 * (RP))
 
-// FP64 value type of the block kernels: double for real storage, c64 for complex.
-template <class T> struct VT { using type = c64; };
-template <> struct VT<double> { using type = double; };
-template <> struct VT<float> { using type = double; };
-template <class T> using Val = typename VT<T>::type;
-
-__device__ inline double vup(double a) { return a; }
-__device__ inline double vup(float a) { return (double)a; }
-__device__ inline c64 vup(c64 a) { return a; }
-__device__ inline c64 vup(c32 a) { return up(a); }
-template <class T> __device__ inline T vdown(double v);
-template <> __device__ inline double vdown<double>(double v) { return v; }
-template <> __device__ inline float vdown<float>(double v) { return (float)v; }
-template <class T> __device__ inline T vdown(c64 v) { return down<T>(v); }
-template <class Vt> __device__ inline Vt vzero();
-template <> __device__ inline double vzero<double>() { return 0.0; }
-template <> __device__ inline c64 vzero<c64>() { return {0.0, 0.0}; }
-__device__ inline double vfma(double a, double b, double c) { return fma(a, b, c); }
-__device__ inline c64 vfma(c64 a, c64 b, c64 c) {
-    return {fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y))};
-}
 __device__ inline double vmul(c64 a, double b) { return a.x * b; }
 __device__ inline c64 vmul(c64 a, c64 b) { return a * b; }
 __device__ inline double vfrom(c64 a, double) { return a.x; }
@@ -782,7 +761,7 @@ __device__ inline void set_bd(Ctl* c) { set_breakdown(c); }
 // 11 (ns + s(s+1)) 2^-53 tr(G); it is raised to 1e3 u tr(G) where that is
 // larger, so that the shifted Q1 (condition number <= (1e3 u)^{-1/2}) is still
 // orthonormal enough, in the stored precision, for the two passes after it.
-__global__ void k_qr_chol(Ctl* c, int slot, int pass, int n, int s, const c64* __restrict__ part2, int p2,
+__global__ __launch_bounds__(kScalar) void k_qr_chol(Ctl* c, int slot, int pass, int n, int s, const c64* __restrict__ part2, int p2,
                           c64* __restrict__ mats, double u) {
     if (stopped(c)) return;
     if (pass == 3 && !c->qr_shift[slot]) return;
@@ -844,7 +823,7 @@ __global__ void k_qr_chol(Ctl* c, int slot, int pass, int n, int s, const c64* _
 }
 
 // Bl-BiCG-rQ: G = V^^H W -> alpha = G^{-1} M, alpha^ = G^{-H} M^H, alpha C.
-__global__ void k_blrq_alpha(Ctl* c, int s, const c64* __restrict__ part2, int p2, c64* __restrict__ mats,
+__global__ __launch_bounds__(kScalar) void k_blrq_alpha(Ctl* c, int s, const c64* __restrict__ part2, int p2, c64* __restrict__ mats,
                              c64* __restrict__ sc) {
     if (stopped(c)) return;
     extern __shared__ c64 dyn[];
@@ -881,7 +860,7 @@ __global__ void k_blrq_alpha(Ctl* c, int s, const c64* __restrict__ part2, int p
 
 // Bl-BiCG-rQ: M' = Q^'^H Q' -> C = S C, C^ = S^ C^, stopping test on ||C||_F,
 // beta = M^{-1} S^^H M', beta^ = M^{-H} S^H M'^H, M = M'.
-__global__ void k_blrq_beta(Ctl* c, double* hist, int s, const c64* __restrict__ part2, int p2,
+__global__ __launch_bounds__(kScalar) void k_blrq_beta(Ctl* c, double* hist, int s, const c64* __restrict__ part2, int p2,
                             c64* __restrict__ mats) {
     if (stopped(c)) return;
     extern __shared__ c64 dyn[];
@@ -931,7 +910,7 @@ __global__ void k_blrq_beta(Ctl* c, double* hist, int s, const c64* __restrict__
 // Initialisation of an rQ method after the first QR (slot 0): C = S, ||C||_F
 // -> control block.  copy_hat: C^ = C (shadow = R0).  Reduced Gram (if p2 > 0)
 // -> mats slot `gslot` (M = Q^H Q or N = R~^H Q).
-__global__ void k_bl_init(Ctl* c, double* hist, int s, int copy_hat, const c64* __restrict__ part2, int p2,
+__global__ __launch_bounds__(kScalar) void k_bl_init(Ctl* c, double* hist, int s, int copy_hat, const c64* __restrict__ part2, int p2,
                           int gslot, c64* __restrict__ mats) {
     if (stopped(c)) return;
     extern __shared__ c64 dyn[];
@@ -965,7 +944,7 @@ __global__ void k_bl_init(Ctl* c, double* hist, int s, int copy_hat, const c64* 
 }
 
 // Bl-BiCGStab-rQ: G = R~^H W -> LU (kept), a = G^{-1} N (stored negated for S~ = Q - W a)
-__global__ void k_blst_a(Ctl* c, int s, const c64* __restrict__ part2, int p2, c64* __restrict__ mats,
+__global__ __launch_bounds__(kScalar) void k_blst_a(Ctl* c, int s, const c64* __restrict__ part2, int p2, c64* __restrict__ mats,
                          c64* __restrict__ sc) {
     if (stopped(c)) return;
     extern __shared__ c64 dyn[];
@@ -991,7 +970,7 @@ __global__ void k_blst_a(Ctl* c, int s, const c64* __restrict__ part2, int p2, c
 
 // Bl-BiCGStab-rQ: (T~^H S~, T~^H T~) -> omega = tr(T~^H S~ K) / tr(T~^H T~ K), K = C C^H;
 // a C and omega C for the X update.
-__global__ void k_blst_omega(Ctl* c, int s, const c64* __restrict__ part2, int p2, c64* __restrict__ mats,
+__global__ __launch_bounds__(kScalar) void k_blst_omega(Ctl* c, int s, const c64* __restrict__ part2, int p2, c64* __restrict__ mats,
                              c64* __restrict__ sc) {
     if (stopped(c)) return;
     extern __shared__ c64 dyn[];
@@ -1037,7 +1016,7 @@ __global__ void k_blst_omega(Ctl* c, int s, const c64* __restrict__ part2, int p
 }
 
 // Bl-BiCGStab-rQ: N' = R~^H Q' -> C = Sigma C, stopping test, b = (1/omega) G^{-1} N', N = N'.
-__global__ void k_blst_b(Ctl* c, double* hist, int s, const c64* __restrict__ part2, int p2,
+__global__ __launch_bounds__(kScalar) void k_blst_b(Ctl* c, double* hist, int s, const c64* __restrict__ part2, int p2,
                          c64* __restrict__ mats, c64* __restrict__ sc) {
     if (stopped(c)) return;
     extern __shared__ c64 dyn[];

@@ -18,6 +18,7 @@ namespace skr {
 
 constexpr int kBlock = 256;      // threads per workgroup for every streaming kernel
 constexpr int kWaves = kBlock / 64;
+constexpr int kScalar = 64;      // one wavefront: the one-workgroup coefficient kernels
 constexpr int kMaxS = 32;        // largest block width the kernels support
 
 struct c64 { double x, y; };
@@ -204,6 +205,28 @@ __device__ inline void sum_partials(const c64* __restrict__ part, int np, c64* r
         res[threadIdx.x] = t;
     }
     __syncthreads();
+}
+
+// FP64 value type of the block kernels and accumulators: double for real storage, c64 for complex.
+template <class T> struct VT { using type = c64; };
+template <> struct VT<double> { using type = double; };
+template <> struct VT<float> { using type = double; };
+template <class T> using Val = typename VT<T>::type;
+
+__device__ inline double vup(double a) { return a; }
+__device__ inline double vup(float a) { return (double)a; }
+__device__ inline c64 vup(c64 a) { return a; }
+__device__ inline c64 vup(c32 a) { return up(a); }
+template <class T> __device__ inline T vdown(double v);
+template <> __device__ inline double vdown<double>(double v) { return v; }
+template <> __device__ inline float vdown<float>(double v) { return (float)v; }
+template <class T> __device__ inline T vdown(c64 v) { return down<T>(v); }
+template <class Vt> __device__ inline Vt vzero();
+template <> __device__ inline double vzero<double>() { return 0.0; }
+template <> __device__ inline c64 vzero<c64>() { return {0.0, 0.0}; }
+__device__ inline double vfma(double a, double b, double c) { return fma(a, b, c); }
+__device__ inline c64 vfma(c64 a, c64 b, c64 c) {
+    return {fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y))};
 }
 
 // ---------------------------------------------------------------- MFMA Gram

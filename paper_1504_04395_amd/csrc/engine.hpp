@@ -21,7 +21,7 @@
 
 namespace skr {
 
-constexpr int kScalar = 64;   // one wavefront for the one-workgroup coefficient kernels
+
 
 struct HipError {
     hipError_t e;

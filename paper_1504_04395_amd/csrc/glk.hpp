@@ -86,7 +86,7 @@ __device__ inline bool end_of_iteration(Ctl* c, double* hist, double res2) {
 // ------------------------------------------------------------------ init
 // Initial residual norm from 2-wide partials (component 0 = ||R0||^2); stops
 // immediately when R0 = 0.
-__global__ void k_init_ctl2(Ctl* c, double* hist, const c64* part, int np) {
+__global__ __launch_bounds__(kScalar) void k_init_ctl2(Ctl* c, double* hist, const c64* part, int np) {
     __shared__ c64 r[2];
     sum_partials<2>(part, np, r);
     if (threadIdx.x == 0) {
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(kBlock) void k_row_mean(int n, int s, const T* __re
 
 // ---------------------------------------------------------- coefficient kernels
 // sigma -> alpha = rho / sigma (Gl-BiCG, eGl-BiCG, Gl-BiCGStab)
-__global__ void k_s_alpha(Ctl* c, const c64* part, int np, c64* sc) {
+__global__ __launch_bounds__(kScalar) void k_s_alpha(Ctl* c, const c64* part, int np, c64* sc) {
     if (stopped(c)) return;
     __shared__ c64 r[1];
     sum_partials<1>(part, np, r);
@@ -169,7 +169,7 @@ __global__ void k_s_alpha(Ctl* c, const c64* part, int np, c64* sc) {
 }
 
 // (||R||^2, rho') -> stopping test, beta = rho'/rho   (Gl-BiCG, eGl-BiCG)
-__global__ void k_s_beta(Ctl* c, double* hist, const c64* part, int np, c64* sc) {
+__global__ __launch_bounds__(kScalar) void k_s_beta(Ctl* c, double* hist, const c64* part, int np, c64* sc) {
     if (stopped(c)) return;
     __shared__ c64 r[2];
     sum_partials<2>(part, np, r);
@@ -183,7 +183,7 @@ __global__ void k_s_beta(Ctl* c, double* hist, const c64* part, int np, c64* sc)
 }
 
 // initial rho = tr(R^H R) (or sum(r^H R)) from partials, component 1
-__global__ void k_s_rho0(const c64* part, int np, int comp, int ncomp, c64* sc) {
+__global__ __launch_bounds__(kScalar) void k_s_rho0(const c64* part, int np, int comp, int ncomp, c64* sc) {
     __shared__ c64 r[2];
     sum_partials<2>(part, np, r);
     if (threadIdx.x == 0) sc[S_RHO] = r[comp];
@@ -289,7 +289,7 @@ __global__ __launch_bounds__(kBlock) void k_stab_s(const Ctl* ctl, Flat fl, cons
 }
 
 // (tr(T^H S), tr(T^H T)) -> omega
-__global__ void k_s_omega(Ctl* c, const c64* part, int np, c64* sc) {
+__global__ __launch_bounds__(kScalar) void k_s_omega(Ctl* c, const c64* part, int np, c64* sc) {
     if (stopped(c)) return;
     __shared__ c64 r[2];
     sum_partials<2>(part, np, r);
@@ -322,7 +322,7 @@ __global__ __launch_bounds__(kBlock) void k_stab_upd(const Ctl* ctl, Flat fl, co
 }
 
 // stopping test, beta = (rho'/rho)(alpha/omega)
-__global__ void k_s_stab_beta(Ctl* c, double* hist, const c64* part, int np, c64* sc) {
+__global__ __launch_bounds__(kScalar) void k_s_stab_beta(Ctl* c, double* hist, const c64* part, int np, c64* sc) {
     if (stopped(c)) return;
     __shared__ c64 r[2];
     sum_partials<2>(part, np, r);
@@ -348,7 +348,7 @@ __global__ __launch_bounds__(kBlock) void k_stab_dir(const Ctl* ctl, Flat fl, co
 // ---------------------------------------------------------- Gl-QMR / eGl-QMR
 // Initial scalars: rho = ||Vt||, xi = ||Wt|| (economic: sqrt(s) ||wt||),
 // delta_raw = tr(Wt^H Vt); part = (||Vt||^2, ||Wt||^2, tr(Wt^H Vt)).
-__global__ void k_qmr_s0(Ctl* c, const c64* part, int np, c64* sc, double xscale) {
+__global__ __launch_bounds__(kScalar) void k_qmr_s0(Ctl* c, const c64* part, int np, c64* sc, double xscale) {
     if (stopped(c)) return;
     __shared__ c64 r[3];
     sum_partials<3>(part, np, r);
@@ -374,7 +374,7 @@ __global__ void k_qmr_s0(Ctl* c, const c64* part, int np, c64* sc, double xscale
 }
 
 // epsilon -> beta = eps / delta
-__global__ void k_qmr_s1(Ctl* c, const c64* part, int np, c64* sc) {
+__global__ __launch_bounds__(kScalar) void k_qmr_s1(Ctl* c, const c64* part, int np, c64* sc) {
     if (stopped(c)) return;
     __shared__ c64 r[1];
     sum_partials<1>(part, np, r);
@@ -388,7 +388,7 @@ __global__ void k_qmr_s1(Ctl* c, const c64* part, int np, c64* sc) {
 
 // (||Vt||^2, ||Wt||^2, tr(Wt^H Vt)) -> theta, gamma, eta, the D/S weight and
 // the next iteration's direction coefficients.
-__global__ void k_qmr_s2(Ctl* c, const c64* part, int np, c64* sc, double xscale) {
+__global__ __launch_bounds__(kScalar) void k_qmr_s2(Ctl* c, const c64* part, int np, c64* sc, double xscale) {
     if (stopped(c)) return;
     __shared__ c64 r[3];
     sum_partials<3>(part, np, r);
@@ -423,7 +423,7 @@ __global__ void k_qmr_s2(Ctl* c, const c64* part, int np, c64* sc, double xscale
 }
 
 // ||R||^2 -> stopping test, then the next iteration's breakdown tests.
-__global__ void k_qmr_s3(Ctl* c, double* hist, const c64* part, int np, c64* sc) {
+__global__ __launch_bounds__(kScalar) void k_qmr_s3(Ctl* c, double* hist, const c64* part, int np, c64* sc) {
     if (stopped(c)) return;
     __shared__ c64 r[1];
     sum_partials<1>(part, np, r);

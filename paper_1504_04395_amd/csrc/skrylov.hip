@@ -96,10 +96,10 @@ __global__ __launch_bounds__(kBlock) void k_xupd(Tile16 tl, const c64* __restric
         store_row<T, J>(X, i, valid, lane, s, x);
     }
 }
-__global__ void k_copy_mat(c64* mats, int s, int from, int to) {
+__global__ __launch_bounds__(kScalar) void k_copy_mat(c64* mats, int s, int from, int to) {
     for (int e = threadIdx.x; e < s * s; e += blockDim.x) mats[(size_t)to * s * s + e] = mats[(size_t)from * s * s + e];
 }
-__global__ void k_sum2(const c64* part, int np, c64* out) {
+__global__ __launch_bounds__(kScalar) void k_sum2(const c64* part, int np, c64* out) {
     __shared__ c64 r[2];
     sum_partials<2>(part, np, r);
     if (threadIdx.x == 0) {

@@ -59,13 +59,37 @@ __device__ inline double sm_frob2(const c64* A, int count, double* red /* unused
     return wave_sum(t);
 }
 
+// Work split of an update over the rows of an s x m array: thread t owns
+// column t % m and rows t / m, t / m + 64 / m, ... (m <= 64), computed once.
+struct Split {
+    int j, r0, rs;
+    bool on;
+};
+__device__ inline Split split_cols(int m) {
+    const int t = threadIdx.x, rs = blockDim.x / m;
+    return {t % m, t / m, rs, t < rs * m};
+}
+
+// One step of an update X[i][j] -= L(i) * x for the rows i = i0, i0 + rs, ...
+// below iend of column j (row stride ldx; L(i) = Lm[i * lds + lk] or the
+// conjugate of Lm[lk * lds + i]).
+template <bool CONJT>
+__device__ inline void sm_axpy_rows(c64* X, int ldx, int j, const c64* Lm, int lds, int lk, c64 x, int i0, int rs,
+                                    int iend) {
+    for (int i = i0; i < iend; i += rs) {
+        const c64 l = CONJT ? conj_(Lm[lk * lds + i]) : Lm[i * lds + lk];
+        X[i * ldx + j] = X[i * ldx + j] - l * x;
+    }
+}
+
 // In-place LU with partial pivoting, P G = L U (unit L below the diagonal, U on
 // and above).  piv[k] = row swapped with k at step k: the first row of largest
 // |re| + |im| in column k (LAPACK's choice).  Returns 1 if U passes the pivot
 // test |u_kk| > s * 2^-52 * max |u_ij| with all entries finite, else 0.
-__device__ inline int sm_lu(c64* A, int* piv, int s, int* flag) {
+__device__ inline int sm_lu(c64* __restrict__ A, int* __restrict__ piv, int s, int* flag) {
     (void)flag;
     const int t = threadIdx.x;
+    const Split sp = split_cols(s);
     for (int k = 0; k < s; ++k) {
         double v = -1.0;
         int idx = k;
@@ -92,14 +116,16 @@ __device__ inline int sm_lu(c64* A, int* piv, int s, int* flag) {
             }
             __syncthreads();
         }
+        // multipliers l_ik = a_ik / a_kk (column k) and the trailing update, in
+        // one step: each updater forms l_ik itself; column k is rewritten after
         const c64 d = A[k * s + k];
-        for (int i = k + 1 + t; i < s; i += blockDim.x) A[i * s + k] = cdiv(A[i * s + k], d);
-        __syncthreads();
-        const int m = s - k - 1;
-        for (int e = t; e < m * m; e += blockDim.x) {
-            const int i = k + 1 + e / m, j = k + 1 + e % m;
-            A[i * s + j] = A[i * s + j] - A[i * s + k] * A[k * s + j];
+        if (sp.on && sp.j > k) {   // a_ij -= (a_ik / d) u_kj
+            const c64 ukj = A[k * s + sp.j];
+            for (int i = k + 1 + sp.r0; i < s; i += sp.rs) A[i * s + sp.j] = A[i * s + sp.j] - cdiv(A[i * s + k], d) * ukj;
         }
+        __syncthreads();
+        if (sp.on && sp.j == k)   // column k is read by the update above, so it is scaled after it
+            for (int i = k + 1 + sp.r0; i < s; i += sp.rs) A[i * s + k] = cdiv(A[i * s + k], d);
         __syncthreads();
     }
     double umax = 0.0;
@@ -118,9 +144,11 @@ __device__ inline int sm_lu(c64* A, int* piv, int s, int* flag) {
 }
 
 // B := G^{-1} B for B s x m (row-major, leading dimension m), G = P^T L U.
-// Row swaps column by column, then forward and back substitution, each step
-// parallel over the entries it updates.
-__device__ inline void sm_lu_solve(const c64* LU, const int* piv, c64* B, int s, int m) {
+// Row swaps column by column; forward substitution with L; back substitution
+// with U where each step uses x_k = b_k / u_kk formed by every updater and row
+// k itself is divided once at the end, so each step needs one barrier.
+__device__ inline void sm_lu_solve(const c64* __restrict__ LU, const int* __restrict__ piv, c64* __restrict__ B,
+                                   int s, int m) {
     const int t = threadIdx.x;
     for (int j = t; j < m; j += blockDim.x)
         for (int k = 0; k < s; ++k) {
@@ -132,45 +160,40 @@ __device__ inline void sm_lu_solve(const c64* LU, const int* piv, c64* B, int s,
             }
         }
     __syncthreads();
+    const Split sp = split_cols(m);
     for (int k = 0; k + 1 < s; ++k) {   // unit lower
-        const int n1 = (s - k - 1) * m;
-        for (int e = t; e < n1; e += blockDim.x) {
-            const int i = k + 1 + e / m, j = e % m;
-            B[i * m + j] = B[i * m + j] - LU[i * s + k] * B[k * m + j];
-        }
+        if (sp.on) sm_axpy_rows<false>(B, m, sp.j, LU, s, k, B[k * m + sp.j], k + 1 + sp.r0, sp.rs, s);
         __syncthreads();
     }
-    for (int k = s - 1; k >= 0; --k) {  // upper
-        for (int j = t; j < m; j += blockDim.x) B[k * m + j] = cdiv(B[k * m + j], LU[k * s + k]);
-        __syncthreads();
-        const int n1 = k * m;
-        for (int e = t; e < n1; e += blockDim.x) {
-            const int i = e / m, j = e % m;
-            B[i * m + j] = B[i * m + j] - LU[i * s + k] * B[k * m + j];
-        }
+    for (int k = s - 1; k > 0; --k) {   // upper
+        if (sp.on) sm_axpy_rows<false>(B, m, sp.j, LU, s, k, cdiv(B[k * m + sp.j], LU[k * s + k]), sp.r0, sp.rs, k);
         __syncthreads();
     }
+    for (int e = t; e < s * m; e += blockDim.x) {
+        const int i = e / m;
+        B[e] = cdiv(B[e], LU[i * s + i]);
+    }
+    __syncthreads();
 }
 
 // B := G^{-H} B, with G = P^T L U, i.e. solve U^H L^H P X = B.
-__device__ inline void sm_lu_solve_h(const c64* LU, const int* piv, c64* B, int s, int m) {
+__device__ inline void sm_lu_solve_h(const c64* __restrict__ LU, const int* __restrict__ piv, c64* __restrict__ B,
+                                     int s, int m) {
     const int t = threadIdx.x;
-    for (int k = 0; k < s; ++k) {       // U^H: lower, diagonal conj(u_kk)
-        for (int j = t; j < m; j += blockDim.x) B[k * m + j] = cdiv(B[k * m + j], conj_(LU[k * s + k]));
-        __syncthreads();
-        const int n1 = (s - k - 1) * m;
-        for (int e = t; e < n1; e += blockDim.x) {
-            const int i = k + 1 + e / m, j = e % m;
-            B[i * m + j] = B[i * m + j] - conj_(LU[k * s + i]) * B[k * m + j];
-        }
+    const Split sp = split_cols(m);
+    for (int k = 0; k + 1 < s; ++k) {   // U^H: lower, diagonal conj(u_kk)
+        if (sp.on)
+            sm_axpy_rows<true>(B, m, sp.j, LU, s, k, cdiv(B[k * m + sp.j], conj_(LU[k * s + k])), k + 1 + sp.r0,
+                               sp.rs, s);
         __syncthreads();
     }
+    for (int e = t; e < s * m; e += blockDim.x) {
+        const int i = e / m;
+        B[e] = cdiv(B[e], conj_(LU[i * s + i]));
+    }
+    __syncthreads();
     for (int k = s - 1; k > 0; --k) {   // L^H: unit upper
-        const int n1 = k * m;
-        for (int e = t; e < n1; e += blockDim.x) {
-            const int i = e / m, j = e % m;
-            B[i * m + j] = B[i * m + j] - conj_(LU[k * s + i]) * B[k * m + j];
-        }
+        if (sp.on) sm_axpy_rows<true>(B, m, sp.j, LU, s, k, B[k * m + sp.j], sp.r0, sp.rs, k);
         __syncthreads();
     }
     for (int j = t; j < m; j += blockDim.x)   // X = P^T W
@@ -192,59 +215,67 @@ __device__ inline void sm_lu_solve_h(const c64* LU, const int* piv, c64* B, int 
 // CholeskyQR callers pass tau = 1e4 u for the first pass (u = unit roundoff of
 // the stored block: a condition number beyond (1e4 u)^{-1/2} would leave the
 // first-pass Q too far from orthonormal for a second pass to repair).
+// Step k updates the trailing part with the unscaled row k divided by the
+// pivot d_k; the rows are scaled by 1 / sqrt(d_k) at the end.
 __device__ inline int sm_cholesky(c64* G, int s, double shift, int* flag /* shared */, double tau) {
     __shared__ double diag0[kMaxS];
+    __shared__ double piv[kMaxS];
     for (int i = threadIdx.x; i < s; i += blockDim.x) {
         G[i * s + i].x += shift;
         G[i * s + i].y = 0.0;
         diag0[i] = G[i * s + i].x;
     }
-    if (threadIdx.x == 0) *flag = 1;
     __syncthreads();
     double dmax = 0.0;
     for (int i = 0; i < s; ++i) dmax = fmax(dmax, diag0[i]);
+    const Split sp = split_cols(s);
+    int ok = 1;
     for (int k = 0; k < s; ++k) {
-        double d = G[k * s + k].x;
-        bool bad = !(d > tau * dmax) || !isfinite(d) || !(diag0[k] > 0.0);
-        if (bad) {
-            if (threadIdx.x == 0) *flag = 0;
-            __syncthreads();
-            break;
+        const double d = G[k * s + k].x;
+        if (!(d > tau * dmax) || !isfinite(d) || !(diag0[k] > 0.0)) {
+            ok = 0;
+            break;   // uniform: every thread reads the same d
         }
-        double r = sqrt(d);
-        __syncthreads();
-        for (int j = k + threadIdx.x; j < s; j += blockDim.x) {
-            if (j == k) G[k * s + k] = {r, 0.0};
-            else G[k * s + j] = (1.0 / r) * G[k * s + j];
-        }
-        __syncthreads();
-        const int m = s - k - 1;
-        for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
-            int i = k + 1 + e / m, j = k + 1 + e % m;
-            if (j >= i) G[i * s + j] = G[i * s + j] - conj_(G[k * s + i]) * G[k * s + j];
-        }
+        if (threadIdx.x == 0) piv[k] = d;
+        if (sp.on && sp.j > k)
+            sm_axpy_rows<true>(G, s, sp.j, G, s, k, (1.0 / d) * G[k * s + sp.j], k + 1 + sp.r0, sp.rs, sp.j + 1);
         __syncthreads();
     }
-    int ok = *flag;
-    for (int e = threadIdx.x; e < s * s; e += blockDim.x) {
-        int i = e / s, j = e - i * s;
-        if (j < i) G[e] = {0.0, 0.0};
+    if (ok) {
+        for (int e = threadIdx.x; e < s * s; e += blockDim.x) {
+            const int i = e / s, j = e - i * s;
+            if (j < i) G[e] = {0.0, 0.0};
+            else if (j == i) G[e] = {sqrt(piv[i]), 0.0};
+            else G[e] = (1.0 / sqrt(piv[i])) * G[e];
+        }
+    } else {
+        for (int e = threadIdx.x; e < s * s; e += blockDim.x) {
+            const int i = e / s, j = e - i * s;
+            if (j < i) G[e] = {0.0, 0.0};
+        }
     }
+    if (threadIdx.x == 0) *flag = ok;
     __syncthreads();
     return ok;
 }
 
-// Sinv = S^{-1} for upper triangular S.  Sinv must not alias S.
-__device__ inline void sm_tri_inv_upper(const c64* S, c64* Sinv, int s) {
-    for (int e = threadIdx.x; e < s * s; e += blockDim.x) Sinv[e] = {0.0, 0.0};
+// Sinv = S^{-1} for upper triangular S (Sinv must not alias S): back
+// substitution on the identity, one barrier per step, diagonal division last.
+__device__ inline void sm_tri_inv_upper(const c64* __restrict__ S, c64* __restrict__ Sinv, int s) {
+    for (int e = threadIdx.x; e < s * s; e += blockDim.x) {
+        const int i = e / s, j = e - i * s;
+        Sinv[e] = {i == j ? 1.0 : 0.0, 0.0};
+    }
     __syncthreads();
-    for (int j = threadIdx.x; j < s; j += blockDim.x) {
-        Sinv[j * s + j] = cdiv(c64{1.0, 0.0}, S[j * s + j]);
-        for (int i = j - 1; i >= 0; --i) {
-            c64 acc = {0.0, 0.0};
-            for (int k = i + 1; k <= j; ++k) acc = acc + S[i * s + k] * Sinv[k * s + j];
-            Sinv[i * s + j] = cdiv(-acc, S[i * s + i]);
-        }
+    const Split sp = split_cols(s);
+    for (int k = s - 1; k > 0; --k) {
+        if (sp.on && sp.j >= k)
+            sm_axpy_rows<false>(Sinv, s, sp.j, S, s, k, cdiv(Sinv[k * s + sp.j], S[k * s + k]), sp.r0, sp.rs, k);
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < s * s; e += blockDim.x) {
+        const int i = e / s;
+        Sinv[e] = cdiv(Sinv[e], S[i * s + i]);
     }
     __syncthreads();
 }

@@ -288,7 +288,8 @@ __global__ __launch_bounds__(kBlock) void k_spmm_csr(const Ctl* ctl, CsrOp<T> A,
 // 2l + 1 (one 16-byte load of X per nonzero for FP64).  A DPP row of 16 lanes
 // carries two matrix rows; the entries of both are loaded 8 at a time (lane u
 // of each half loads entry u) and broadcast inside their half.  A wave owns 16
-// consecutive rows per pass (two passes of 8).  The matrix stream (indices,
+// consecutive rows per pass (two passes of 8); products are accumulated in FP64
+// also for FP32 data.  The matrix stream (indices,
 // values) is read and Y is written with non-temporal hints, so that L2 keeps
 // the X rows that neighbouring matrix rows gather again.  Epilogues see the
 // tile-16 layout: the wave's 16 x 16 result tile goes through LDS and each
@@ -339,7 +340,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_csr8(const Ctl* ctl, CsrOp<T> A
             k0[p] = valid[p] ? A.rp[i[p]] : 0;
             k1[p] = valid[p] ? A.rp[i[p] + 1] : 0;
         }
-        T ax[2] = {T(0), T(0)}, ay[2] = {T(0), T(0)};
+        double ax[2] = {0.0, 0.0}, ay[2] = {0.0, 0.0};   // FP64 accumulation, also for FP32 data
         for (int off = 0;; off += U) {
             int mc[2];
             T ma[2];
@@ -363,8 +364,8 @@ __global__ __launch_bounds__(kBlock) void k_spmm_csr8(const Ctl* ctl, CsrOp<T> A
                     const int c = half ? c1 : c0;
                     const T a = half ? a1 : a0;
                     const P2 xv = *reinterpret_cast<const P2*>(X + (size_t)c * s + cofs);
-                    ax[p] = fma_(a, xv.x, ax[p]);
-                    ay[p] = fma_(a, xv.y, ay[p]);
+                    ax[p] = fma((double)a, (double)xv.x, ax[p]);
+                    ay[p] = fma((double)a, (double)xv.y, ay[p]);
                 });
             }
             if (!more) break;
@@ -373,8 +374,8 @@ __global__ __launch_bounds__(kBlock) void k_spmm_csr8(const Ctl* ctl, CsrOp<T> A
         for (int p = 0; p < 2; ++p) {
             if (valid[p] && colok) {
                 T* yr = Y + (size_t)i[p] * s + 2 * l8;
-                __builtin_nontemporal_store(ax[p], yr);
-                __builtin_nontemporal_store(ay[p], yr + 1);
+                __builtin_nontemporal_store((T)ax[p], yr);
+                __builtin_nontemporal_store((T)ay[p], yr + 1);
             }
         }
         if constexpr (EPI) {
@@ -382,8 +383,8 @@ __global__ __launch_bounds__(kBlock) void k_spmm_csr8(const Ctl* ctl, CsrOp<T> A
 #pragma unroll
             for (int p = 0; p < 2; ++p) {
                 const int lr = 8 * p + 2 * g + half;
-                tw[lr * 17 + 2 * l8] = colok ? ax[p] : T(0);
-                tw[lr * 17 + 2 * l8 + 1] = colok ? ay[p] : T(0);
+                tw[lr * 17 + 2 * l8] = colok ? (T)ax[p] : T(0);       // the stored (rounded) values
+                tw[lr * 17 + 2 * l8 + 1] = colok ? (T)ay[p] : T(0);
             }
             __builtin_amdgcn_wave_barrier();
             const Layout l16{s, 16, 4};
@@ -410,7 +411,8 @@ __global__ __launch_bounds__(kBlock) void k_spmm_csr8(const Ctl* ctl, CsrOp<T> A
 
 // Single vector (s = 1): y = A x with 8 lanes per row.  Lane e of a row's group
 // takes entries k0 + e, k0 + e + 8, ... and the 8 partial sums are added by a
-// butterfly inside the group.  Same per-XCD row sweep as k_spmm_csr.
+// butterfly inside the group, in FP64 whatever the storage precision.  Same
+// per-XCD row sweep as k_spmm_csr.
 __device__ inline double shfl_xor_v(double v, int off) { return __shfl_xor(v, off, 64); }
 __device__ inline float shfl_xor_v(float v, int off) { return __shfl_xor(v, off, 64); }
 __device__ inline c64 shfl_xor_v(c64 v, int off) { return {__shfl_xor(v.x, off, 64), __shfl_xor(v.y, off, 64)}; }
@@ -430,12 +432,13 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr(const Ctl* ctl, CsrOp<T> A,
         const bool valid = i < r1;                         // uniform inside the 8-lane group
         const int k0 = valid ? A.rp[i] : 0;
         const int k1 = valid ? A.rp[i + 1] : 0;
-        T acc = zero<T>();
-        for (int k = k0 + sub; k < k1; k += 8) acc = fma_(A.va[k], x[A.ci[k]], acc);
+        using W = Val<T>;   // double or c64
+        W acc = vzero<W>();
+        for (int k = k0 + sub; k < k1; k += 8) acc = vfma(vup(A.va[k]), vup(x[A.ci[k]]), acc);
         acc = acc + shfl_xor_v(acc, 4);
         acc = acc + shfl_xor_v(acc, 2);
         acc = acc + shfl_xor_v(acc, 1);
-        if (valid && sub == 0) y[i] = acc;
+        if (valid && sub == 0) y[i] = vdown<T>(acc);
     }
 }
 
