@@ -115,6 +115,10 @@ __device__ inline double rbc(double v) {
 template <int N>
 __device__ inline c64 rbc(c64 v) { return {rbc<N>(v.x), rbc<N>(v.y)}; }
 
+// value of lane `src` of this lane's 16-lane row group
+__device__ inline double shfl16(double v, int src) { return __shfl(v, src, 16); }
+__device__ inline c64 shfl16(c64 v, int src) { return {__shfl(v.x, src, 16), __shfl(v.y, src, 16)}; }
+
 template <int A, int END, class F>
 __device__ inline void static_for(F&& f) {
     if constexpr (A < END) {
@@ -152,16 +156,18 @@ struct Coef {
             });
             out[0] = acc;
         } else {
+            // rolled loop over the s coefficients (a full unroll of 16 J
+            // broadcasts would keep too many values live); column a of the row
+            // comes from lane a % 16 of the row group by a lane shuffle
             int cc[J];
 #pragma unroll
             for (int j = 0; j < J; ++j) cc[j] = min(lane + 16 * j, s - 1);
-            static_for<0, 16 * J>([&](auto ic) {
-                constexpr int a = decltype(ic)::value;
-                const VV xa = rbc<a % 16>(x[a / 16]);
-                const int ar = min(a, s - 1) * s;
+            for (int a = 0; a < s; ++a) {
+                const VV xa = shfl16((J == 1 || a < 16) ? x[0] : x[J - 1], a & 15);
+                const int ar = a * s;
 #pragma unroll
                 for (int j = 0; j < J; ++j) out[j] = vfma(xa, M[ar + cc[j]], out[j]);
-            });
+            }
 #pragma unroll
             for (int j = 0; j < J; ++j)
                 if (lane + 16 * j >= s) out[j] = vzero<VV>();
@@ -173,7 +179,8 @@ struct Coef {
 // part[b] = L^H R over this workgroup's rows
 template <class T, int J>
 __global__ __launch_bounds__(kBlock) void k_bl_gram(const Ctl* ctl, Tile16 tl, const T* __restrict__ Lm,
-                                                    const T* __restrict__ Rm, c64* part) {
+                                                    const T* __restrict__ Rm, c64* part, int pstride = 0,
+                                                    int poff = 0) {
     if (stopped(ctl)) return;
     constexpr int RP = RowPasses<T, J>::value;
     GramAcc<J, Tr<T>::cplx> g;
@@ -190,7 +197,7 @@ __global__ __launch_bounds__(kBlock) void k_bl_gram(const Ctl* ctl, Tile16 tl, c
         for (int p = 0; p < RP; ++p) g.add(l[p], r[p]);
     }
     __shared__ c64 lds[(16 * J) * (16 * J)];
-    g.store(tl.s, lds, part + (size_t)blockIdx.x * tl.s * tl.s);
+    g.store(tl.s, lds, part + (size_t)blockIdx.x * (pstride > 0 ? pstride : tl.s * tl.s) + poff);
 }
 
 // Second reduction stage: per-workgroup partials [np][E] -> out[E].  One wave

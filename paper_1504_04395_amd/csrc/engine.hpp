@@ -126,7 +126,23 @@ void spmm_j(Env<T>& e, const Operand<T>& op, const Layout& ly, const T* X, T* Y,
         const Layout l16{ly.s, 16, 4};
         const int step = 32;                           // RP * 16 rows per workgroup pass (upper bound)
         const int per_xcd = ((e.n + 7) / 8 + step - 1) / step * step;
-        k_spmm_csr<T, J16, Epi><<<e.nb, kBlock, 0, e.st>>>(ctl, op.csr, l16, per_xcd, X, Y, epi);
+        if constexpr (J16 == 2 && EpiIsGram<Epi>::value && J == 2) {
+            // s > 16: the fused s x s Gram accumulators would cut the gather
+            // loop's occupancy to 1-2 waves per SIMD, so the product runs
+            // alone and the Gram is a separate streaming pass over Y and Z
+            k_spmm_csr<T, 2, EpiNone><<<e.nb, kBlock, 0, e.st>>>(ctl, op.csr, l16, per_xcd, X, Y, EpiNone{});
+            SKR_LAUNCHED();
+            const int ss = ly.s * ly.s;
+            if constexpr (std::is_same<Epi, EpiGram<T, 2>>::value) {
+                k_bl_gram<T, 2><<<e.nb, kBlock, 0, e.st>>>(ctl, e.tl, epi.Z, Y, epi.part);   // Z^H Y
+            } else {
+                k_bl_gram<T, 2><<<e.nb, kBlock, 0, e.st>>>(ctl, e.tl, Y, epi.Z, epi.part, 2 * ss, 0);   // Y^H Z
+                SKR_LAUNCHED();
+                k_bl_gram<T, 2><<<e.nb, kBlock, 0, e.st>>>(ctl, e.tl, Y, Y, epi.part, 2 * ss, ss);      // Y^H Y
+            }
+        } else {
+            k_spmm_csr<T, J16, Epi><<<e.nb, kBlock, 0, e.st>>>(ctl, op.csr, l16, per_xcd, X, Y, epi);
+        }
     }
     SKR_LAUNCHED();
 }
