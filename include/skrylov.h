@@ -58,7 +58,10 @@ typedef enum {
     SKR_EGL_QMR = 3,          /* Section 4 (economic global QMR) */
     SKR_GL_BICGSTAB = 4,      /* Sections 2-3 (global BiCGStab) */
     SKR_BL_BICG_RQ = 5,       /* Algorithm 5 */
-    SKR_BL_BICGSTAB_RQ = 6    /* Section 4, closing paragraph */
+    SKR_BL_BICGSTAB_RQ = 6,   /* Section 4, closing paragraph */
+    SKR_BL_BICG = 7,          /* Algorithm 3 (block BiCG without QR of the residual) */
+    SKR_BL_BICGSTAB = 8,      /* block BiCGStab of El Guennouni et al. (Sections 3 and 5.2) */
+    SKR_LI_BICG = 9           /* Algorithm 1 (loop-interchanged: s independent BiCG) */
 } skr_method;
 
 typedef enum { SKR_F64 = 0, SKR_C64 = 1 } skr_dtype;

@@ -35,6 +35,7 @@ enum {
     M_S1, M_S1INV, M_S12, M_S2INV, M_S, M_S3INV,          // QR slot 0 work (M_S: R factor)
     M_T1, M_T1INV, M_T12, M_T2INV, M_T, M_T3INV,          // QR slot 1 work (M_T: R factor)
     M_N, M_A, M_AC, M_WC, M_B, M_RB, M_TMP,
+    M_G1, M_RR, M_RHR, M_RT, M_W, M_MW,                   // plain Bl-BiCG / Bl-BiCGStab / Li-BiCG
     M_COUNT
 };
 enum { SC_GAMMA = 40, SC_OMEGA = 41, SC_PIV = 48 };   // scalars / pivots inside sc[]

@@ -17,6 +17,7 @@
 #include "blk.hpp"
 #include "common.hpp"
 #include "glk.hpp"
+#include "pln.hpp"
 #include "spmm.hpp"
 
 namespace skr {
@@ -530,6 +531,119 @@ Method<T> make_bl_bicgstab_rq(Env<T>& e, Arena& ar, T* rhs, T* x) {
         reduce2(e, ss);
         k_blst_b<<<1, kScalar, 4 * (size_t)ss * sizeof(c64), e.st>>>(e.ctl, e.hist, s, e.part2, e.p2, e.mats, e.sc);
         axpm<T, J, false>(e, M_B, SC_GAMMA, Q, U, W, U);                           // U = Q + (U - omega W) b
+    };
+    return m;
+}
+
+// Block BiCG (Algorithm 3, all four s x s coefficient matrices from their own
+// Gram matrices) and, with diag = 1, loop-interchanged BiCG (Algorithm 1): the
+// same schedule with the diagonals of the Gram matrices, i.e. s independent
+// BiCG recurrences (alpha^ = conj(alpha), beta^ = conj(beta)).
+template <class T, int J>
+Method<T> make_bl_bicg(Env<T>& e, Arena& ar, T* rhs, T* x, int diag) {
+    Method<T> m;
+    T* R = (T*)ar.take(e.blk_bytes());
+    T* Rh = (T*)ar.take(e.blk_bytes());
+    T* P = (T*)ar.take(e.blk_bytes());
+    T* Ph = (T*)ar.take(e.blk_bytes());
+    T* Q = (T*)ar.take(e.blk_bytes());
+    T* Qh = (T*)ar.take(e.blk_bytes());
+    m.mv_per_iter = 2LL * e.s;
+    const int s = e.s, ss = s * s;
+    const Layout lt = tile_layout(e);
+    const size_t lds3 = 3 * (size_t)ss * sizeof(c64);
+    m.init = [=, &e]() {
+        k_copy<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, rhs, R, Rh, P);
+        k_copy<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, rhs, Ph, nullptr, nullptr);
+        k_fill0<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, x, nullptr, nullptr, nullptr);
+        k_flat_nrm_dot<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, R, nullptr, e.part);
+        k_init_ctl2<<<1, kScalar, 0, e.st>>>(e.ctl, e.hist, e.part, e.nb);
+        k_bl_gram<T, J><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.tl, Rh, R, e.part);   // R^^H R
+        SKR_LAUNCHED();
+        reduce2(e, ss);
+        k_stash<<<1, kScalar, 0, e.st>>>(e.ctl, e.part2, e.p2, s, e.mats, M_RHR);
+        SKR_LAUNCHED();
+    };
+    m.iter = [=, &e]() {
+        spmm_j<T, J>(e, e.A, lt, P, Q, EpiGram<T, J>{Ph, e.part}, e.ctl);           // Q = A P, G1 = P^^H Q
+        reduce2(e, ss);
+        k_stash<<<1, kScalar, 0, e.st>>>(e.ctl, e.part2, e.p2, s, e.mats, M_G1);
+        SKR_LAUNCHED();
+        if (diag) {
+            spmm_j<T, J>(e, e.AH, lt, Ph, Qh, EpiNone{}, e.ctl);                    // Q^ = A^H P^
+        } else {
+            spmm_j<T, J>(e, e.AH, lt, Ph, Qh, EpiGram<T, J>{P, e.part}, e.ctl);     // Q^ = A^H P^, G2 = P^H Q^
+            reduce2(e, ss);
+        }
+        k_blb_alpha<<<1, kScalar, lds3, e.st>>>(e.ctl, s, diag, e.part2, e.p2, e.mats);
+        SKR_LAUNCHED();
+        axpm<T, J, false>(e, M_ALPHA, 0, x, P, nullptr, x);                         // X += P alpha
+        axpm<T, J, true>(e, M_TMP, 0, R, Q, nullptr, R);                            // R -= Q alpha, R^H R
+        reduce2(e, ss);
+        k_stash<<<1, kScalar, 0, e.st>>>(e.ctl, e.part2, e.p2, s, e.mats, M_RR);
+        SKR_LAUNCHED();
+        axpm<T, J, false>(e, M_ALPHAH, 0, Rh, Qh, nullptr, Rh);                     // R^ -= Q^ alpha^
+        k_bl_gram<T, J><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.tl, Rh, R, e.part);     // R^^H R
+        SKR_LAUNCHED();
+        reduce2(e, ss);
+        k_blb_beta<<<1, kScalar, lds3, e.st>>>(e.ctl, e.hist, s, diag, e.part2, e.p2, e.mats);
+        SKR_LAUNCHED();
+        axpm<T, J, false>(e, M_BETA, 0, R, P, nullptr, P);                          // P = R + P beta
+        axpm<T, J, false>(e, M_BETAH, 0, Rh, Ph, nullptr, Ph);                      // P^ = R^ + P^ beta^
+    };
+    return m;
+}
+
+// Block BiCGStab (El Guennouni et al.): s x s alpha and beta, scalar omega.
+template <class T, int J>
+Method<T> make_bl_bicgstab(Env<T>& e, Arena& ar, T* rhs, T* x) {
+    Method<T> m;
+    T* R = (T*)ar.take(e.blk_bytes());
+    T* Rt = (T*)ar.take(e.blk_bytes());
+    T* P = (T*)ar.take(e.blk_bytes());
+    T* V = (T*)ar.take(e.blk_bytes());
+    T* S = (T*)ar.take(e.blk_bytes());
+    T* Tm = (T*)ar.take(e.blk_bytes());
+    m.mv_per_iter = 2LL * e.s;
+    const int s = e.s, ss = s * s;
+    const Layout lt = tile_layout(e);
+    const size_t lds4 = 4 * (size_t)ss * sizeof(c64);
+    m.init = [=, &e]() {
+        k_copy<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, rhs, R, Rt, P);
+        k_fill0<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, x, nullptr, nullptr, nullptr);
+        k_flat_nrm_dot<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, R, nullptr, e.part);
+        k_init_ctl2<<<1, kScalar, 0, e.st>>>(e.ctl, e.hist, e.part, e.nb);
+        k_bl_gram<T, J><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.tl, Rt, R, e.part);    // N = R~^H R
+        SKR_LAUNCHED();
+        reduce2(e, ss);
+        k_stash<<<1, kScalar, 0, e.st>>>(e.ctl, e.part2, e.p2, s, e.mats, M_N);
+        SKR_LAUNCHED();
+    };
+    m.iter = [=, &e]() {
+        spmm_j<T, J>(e, e.A, lt, P, V, EpiGram<T, J>{Rt, e.part}, e.ctl);           // V = A P, G = R~^H V
+        reduce2(e, ss);
+        k_blst_a<<<1, kScalar, lds4, e.st>>>(e.ctl, s, e.part2, e.p2, e.mats, e.sc); // alpha = G^{-1} N
+        SKR_LAUNCHED();
+        axpm<T, J, false>(e, M_TMP, 0, R, V, nullptr, S);                           // S = R - V alpha
+        spmm(e, e.A, e.ly, S, Tm, EpiTraceOmega<T>{S, e.part}, e.ctl);              // T = A S
+        k_blbs_omega<<<1, kScalar, 0, e.st>>>(e.ctl, s, e.part, e.nb, e.sc, e.mats);
+        SKR_LAUNCHED();
+        axpm<T, J, false>(e, M_A, 0, x, P, nullptr, x);                             // X += P alpha
+        axpm<T, J, false>(e, M_W, 0, x, S, nullptr, x);                             // X += omega S
+        axpm<T, J, true>(e, M_MW, 0, S, Tm, nullptr, R);                            // R = S - omega T, R^H R
+        reduce2(e, ss);
+        k_stash<<<1, kScalar, 0, e.st>>>(e.ctl, e.part2, e.p2, s, e.mats, M_RR);
+        k_bl_gram<T, J><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.tl, Rt, Tm, e.part);    // R~^H T
+        SKR_LAUNCHED();
+        reduce2(e, ss);
+        k_stash<<<1, kScalar, 0, e.st>>>(e.ctl, e.part2, e.p2, s, e.mats, M_RT);
+        k_bl_gram<T, J><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.tl, Rt, R, e.part);     // N' = R~^H R
+        SKR_LAUNCHED();
+        reduce2(e, ss);
+        k_blbs_beta<<<1, kScalar, 2 * (size_t)ss * sizeof(c64), e.st>>>(e.ctl, e.hist, s, e.part2, e.p2, e.mats,
+                                                                          e.sc);
+        SKR_LAUNCHED();
+        axpm<T, J, false>(e, M_B, SC_GAMMA, R, P, V, P);                            // P = R + (P - omega V) beta
     };
     return m;
 }
