@@ -257,6 +257,113 @@ def unit_block(n: int, s: int, complex_: bool = True) -> np.ndarray:
     return B
 
 
+# ---------------------------------------------------------------------------
+# The paper's Examples 1-3 (Section 5.1), central differences on an equispaced
+# interior grid, all rows multiplied by h^2, x fastest.  Only the structure the
+# section fixes is reproduced: the discretisation details it leaves open (and
+# the preconditioners of its second table) are not.
+# ---------------------------------------------------------------------------
+def _grid_coords(shape):
+    n = int(np.prod(shape))
+    idx = np.arange(n, dtype=np.int64)
+    out, stride = [], 1
+    for m in shape:
+        out.append((idx // stride) % m)
+        stride *= m
+    return out
+
+
+def paper_example1(m: int = 200, alpha=(5.0, 5.0, 5.0)):
+    """Example 1: -u_xx - u_yy + 2 a1 u_x + 2 a2 u_y - 2 a3 u = 0 on the unit square
+    (a1 = a2 = a3 = 5), m x m interior points, h = 1/(m+1).  Four right-hand
+    sides, one per corner: Dirichlet data continuous and piecewise linear along
+    the boundary, 1 at that corner and 0 at the other three.  A boundary value
+    g enters the row of its interior neighbour as -(coupling) * g."""
+    a1, a2, a3 = alpha
+    h = 1.0 / (m + 1)
+    west, east = -1.0 - a1 * h, -1.0 + a1 * h
+    south, north = -1.0 - a2 * h, -1.0 + a2 * h
+    A = _stencil((m, m), 4.0 - 2.0 * a3 * h * h, [west, south], [east, north])
+    ix, iy = _grid_coords((m, m))
+    x = (ix + 1) * h
+    y = (iy + 1) * h
+    corners = [(0.0, 0.0), (1.0, 0.0), (0.0, 1.0), (1.0, 1.0)]
+
+    def g(cx, cy, px, py):
+        # hat function of the corner along the boundary: linear on each edge
+        return np.maximum(0.0, 1.0 - np.abs(px - cx) - np.abs(py - cy)) * \
+            ((np.isclose(px, cx)) | (np.isclose(py, cy)))
+
+    B = np.zeros((m * m, 4))
+    for k, (cx, cy) in enumerate(corners):
+        b = np.zeros(m * m)
+        b -= np.where(ix == 0, west * g(cx, cy, 0.0 * x, y), 0.0)
+        b -= np.where(ix == m - 1, east * g(cx, cy, 0.0 * x + 1.0, y), 0.0)
+        b -= np.where(iy == 0, south * g(cx, cy, x, 0.0 * y), 0.0)
+        b -= np.where(iy == m - 1, north * g(cx, cy, x, 0.0 * y + 1.0), 0.0)
+        B[:, k] = b
+    return A, B
+
+
+def paper_example2(m: int = 50, nu: float = 1000.0):
+    """Example 2 (Example 3 with nu = 10): u_xx + u_yy + u_zz + nu u_x = f on the
+    unit cube, m^3 interior points, h = 1/(m+1); the rows are multiplied by
+    -h^2 (centre 6, x-neighbours -1 -/+ nu h / 2, others -1).  19 right-hand
+    sides: f from the exact solution u = exp(xyz) sin(pi x) sin(pi y) sin(pi z)
+    with zero boundary data, and 18 with f = 0 and, on one face at a time, the
+    boundary data equal to each of its two tangential coordinates and to 1."""
+    h = 1.0 / (m + 1)
+    c = nu * h / 2.0
+    minus = [-1.0 + c, -1.0, -1.0]       # -(1 - nu h / 2) for the west neighbour
+    plus = [-1.0 - c, -1.0, -1.0]        # -(1 + nu h / 2) for the east neighbour
+    A = _stencil((m, m, m), 6.0, minus, plus)
+    ix, iy, iz = _grid_coords((m, m, m))
+    x, y, z = (ix + 1) * h, (iy + 1) * h, (iz + 1) * h
+    n = m ** 3
+    cols = []
+    # f = Laplace(u) + nu u_x for u = exp(xyz) sin(pi x) sin(pi y) sin(pi z)
+    e = np.exp(x * y * z)
+    sx, sy, sz = np.sin(np.pi * x), np.sin(np.pi * y), np.sin(np.pi * z)
+    cx_, cy_, cz_ = np.cos(np.pi * x), np.cos(np.pi * y), np.cos(np.pi * z)
+    pi = np.pi
+
+    def d2(a, b, c_, s_, co):   # second derivative along the axis with product coordinate a*b
+        return e * ((a * b) ** 2 * s_ + 2 * pi * a * b * co - pi * pi * s_)
+
+    uxx = d2(y, z, None, sx, cx_) * sy * sz
+    uyy = d2(x, z, None, sy, cy_) * sx * sz
+    uzz = d2(x, y, None, sz, cz_) * sx * sy
+    ux = e * (y * z * sx + pi * cx_) * sy * sz
+    f = uxx + uyy + uzz + nu * ux
+    cols.append(-h * h * f)
+    coord = {"x": x, "y": y, "z": z}
+    faces = [("x", 0, ix == 0, minus[0]), ("x", 1, ix == m - 1, plus[0]),
+             ("y", 0, iy == 0, minus[1]), ("y", 1, iy == m - 1, plus[1]),
+             ("z", 0, iz == 0, minus[2]), ("z", 1, iz == m - 1, plus[2])]
+    for axis, side, mask, coup in faces:
+        tang = [a for a in ("x", "y", "z") if a != axis]
+        for gfun in (coord[tang[0]], coord[tang[1]], np.ones(n)):
+            cols.append(np.where(mask, -coup * gfun, 0.0))
+    return A, np.stack(cols, axis=1)
+
+
+def paper_example(k: int, scale: str = "full") -> Problem:
+    """Examples 1-3 of Section 5.1 (full size: 200^2 with s = 4; 50^3 with
+    s = 19).  ``scale='small'`` keeps the equations and right-hand sides on a
+    coarser grid (40^2, 12^3)."""
+    small = scale == "small"
+    if k == 1:
+        A, B = paper_example1(40 if small else 200)
+        name = "paper-ex1"
+    elif k in (2, 3):
+        A, B = paper_example2(12 if small else 50, 1000.0 if k == 2 else 10.0)
+        name = f"paper-ex{k}"
+    else:
+        raise ValueError(k)
+    return Problem(name + ("-small" if small else ""), A, B,
+                   ("bl_bicg", "bl_bicg_rq", "bl_bicgstab", "bl_bicgstab_rq"), {})
+
+
 @dataclass
 class Problem:
     name: str

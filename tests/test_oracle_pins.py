@@ -491,3 +491,47 @@ def test_sddmm_oracle():
             assert abs(out[p] - dense[i, C.indices[p]]) < 1e-13
             k += 1
     assert k == C.nnz
+
+
+# ---------------------------------------------------------------------------
+# The paper's Examples 1-3 (Section 5.1): sizes against Table 1, the exact
+# solution of Example 2/3's first right-hand side, and the corner data of
+# Example 1 summing to constant boundary data
+# ---------------------------------------------------------------------------
+def test_paper_examples_rho_match_table1():
+    golden = {r[0]: r[3] for r in _table1()}
+    for k in (1, 2, 3):
+        P = I.paper_example(k)
+        rho = P.B.shape[1] * P.A.n / P.A.nnz
+        assert abs(rho - golden[f"ex{k}"]) < 0.01, (k, rho)
+
+
+def test_paper_example3_first_rhs_has_the_stated_solution():
+    """Example 3 (nu = 10): the discrete solution of the first right-hand side
+    approaches u = exp(xyz) sin(pi x) sin(pi y) sin(pi z) at second order."""
+    import scipy.sparse.linalg as spla
+    errs = []
+    for m in (10, 20):
+        A, B = I.paper_example2(m, nu=10.0)
+        u = spla.spsolve(A.to_scipy().tocsc(), B[:, 0])
+        h = 1.0 / (m + 1)
+        g = (np.arange(m) + 1) * h
+        x, y, z = np.meshgrid(g, g, g, indexing="ij")
+        ue = (np.exp(x * y * z) * np.sin(np.pi * x) * np.sin(np.pi * y) * np.sin(np.pi * z)).transpose(2, 1, 0).ravel()
+        errs.append(np.abs(u - ue).max() / np.abs(ue).max())
+    assert errs[1] < 3e-3
+    assert 3.0 < errs[0] / errs[1] < 5.0      # second-order convergence: ratio ~ ((21/11)^2 = 3.6)
+
+
+def test_paper_example1_corner_data_partition_of_unity():
+    """The four corner data sum to boundary data 1 on the whole boundary, whose
+    right-hand side is minus the boundary couplings of each row."""
+    m = 17
+    A, B = I.paper_example1(m)
+    h = 1.0 / (m + 1)
+    west, east, south, north = -1 - 5 * h, -1 + 5 * h, -1 - 5 * h, -1 + 5 * h
+    ix = np.arange(m * m) % m
+    iy = np.arange(m * m) // m
+    b1 = -(west * (ix == 0) + east * (ix == m - 1) + south * (iy == 0) + north * (iy == m - 1))
+    np.testing.assert_allclose(B.sum(axis=1), b1, rtol=0, atol=1e-14)
+    assert np.all(B >= 0)
