@@ -555,7 +555,7 @@ def bl_bicgstab_rq(A, AH, R0, tol, maxit, shadow=None, hook=None):
 
 
 # ----------------------------------------------------------------------------
-# Loop-interchanged BiCG, Algorithm 1 (used only as an s = 1 cross-check)
+# Loop-interchanged BiCG, Algorithm 1
 # ----------------------------------------------------------------------------
 def li_bicg(A, AH, R0, tol, maxit, shadow=None, hook=None):
     """Loop-interchanged BiCG (Algorithm 1): s independent BiCG recurrences with
@@ -602,6 +602,137 @@ def li_bicg(A, AH, R0, tol, maxit, shadow=None, hook=None):
     return X, info
 
 
+def _cdot(Y: np.ndarray, X: np.ndarray) -> np.ndarray:
+    """Column-wise inner products y_j^H x_j (one per right-hand side)."""
+    return np.einsum("ij,ij->j", np.conj(Y), X)
+
+
+def _denominators(d) -> None:
+    for v in np.atleast_1d(d):
+        _denominator(v)
+
+
+# ----------------------------------------------------------------------------
+# Loop-interchanged QMR and BiCGStab (Section 2: the s single-RHS recurrences
+# run side by side, their products with A gathered into one block product)
+# ----------------------------------------------------------------------------
+def li_qmr(A, AH, R0, tol, maxit, shadow=None, hook=None):
+    """Loop-interchanged QMR: column j runs the QMR of ``_qmr`` (Freund &
+    Nachtigal, no look-ahead, coupled two-term form) on A x_j = r0_j with its own
+    scalars rho_j, xi_j, delta_j, eps_j, beta_j, theta_j, gamma_j, eta_j.  The
+    block residual R <- R - S is carried for the common stopping rule."""
+    s = R0.shape[1]
+    info = _Info()
+    X = np.zeros_like(R0)
+    R = R0.copy()
+    nr0 = _fro(R0)
+    info.history.append(1.0)
+    if nr0 == 0:
+        info.status = STATUS_OK
+        return X, info
+    Vt = R0.copy()
+    Wt = R0.copy() if shadow is None else np.array(shadow, dtype=R0.dtype)
+    rho = np.linalg.norm(Vt, axis=0)
+    xi = np.linalg.norm(Wt, axis=0)
+    gamma_p, eta_p, theta_p, eps_p = np.ones(s), -np.ones(s, dtype=R0.dtype), np.zeros(s), None
+    P = Qd = D = S = None
+    try:
+        for i in range(maxit):
+            _denominators(rho)
+            _denominators(xi)
+            V = Vt / rho[None, :]
+            W = Wt / xi[None, :]
+            delta = _cdot(W, V)
+            _denominators(delta)
+            if i == 0:
+                P, Qd = V.copy(), W.copy()
+            else:
+                _denominators(eps_p)
+                P = V - P * (xi * delta / eps_p)[None, :]
+                Qd = W - Qd * np.conj(rho * delta / eps_p)[None, :]
+            Pt = A @ P
+            eps = _cdot(Qd, Pt)
+            _denominators(eps)
+            beta = eps / delta
+            Vt = Pt - V * beta[None, :]
+            Wt = AH @ Qd - W * np.conj(beta)[None, :]
+            info.matvecs += 2 * s
+            rho_n = np.linalg.norm(Vt, axis=0)
+            xi_n = np.linalg.norm(Wt, axis=0)
+            _denominators(beta)
+            _denominators(gamma_p)
+            theta = rho_n / (gamma_p * np.abs(beta))
+            gamma = 1.0 / np.sqrt(1.0 + theta * theta)
+            _denominators(gamma)
+            eta = -eta_p * rho * gamma * gamma / (beta * gamma_p * gamma_p)
+            if i == 0:
+                D = P * eta[None, :]
+                S = Pt * eta[None, :]
+            else:
+                f = (theta_p * gamma) ** 2
+                D = P * eta[None, :] + D * f[None, :]
+                S = Pt * eta[None, :] + S * f[None, :]
+            X = X + D
+            R = R - S
+            if hook:
+                hook(i + 1, X, {})
+            if _finish(info, _fro(R), nr0, tol, i + 1):
+                return X, info
+            rho, xi, gamma_p, eta_p, theta_p, eps_p = rho_n, xi_n, gamma, eta, theta, eps
+    except _Breakdown:
+        info.status = STATUS_BREAKDOWN
+        info.breakdown_iter = info.iterations
+    return X, info
+
+
+def li_bicgstab(A, AH, R0, tol, maxit, shadow=None, hook=None):
+    """Loop-interchanged BiCGStab: column j runs van der Vorst's BiCGStab on
+    A x_j = r0_j (shadow r~_j = r0_j) with its own alpha_j, omega_j, beta_j;
+    the two products per step are block products.  Convergence is tested on
+    the block residual after full steps only."""
+    s = R0.shape[1]
+    info = _Info()
+    X = np.zeros_like(R0)
+    R = R0.copy()
+    Rt = R0.copy() if shadow is None else np.array(shadow, dtype=R0.dtype)
+    P = R.copy()
+    nr0 = _fro(R0)
+    info.history.append(1.0)
+    if nr0 == 0:
+        info.status = STATUS_OK
+        return X, info
+    rho = _cdot(Rt, R)
+    try:
+        for k in range(maxit):
+            V = A @ P
+            info.matvecs += s
+            sigma = _cdot(Rt, V)
+            _denominators(sigma)
+            alpha = rho / sigma
+            S = R - V * alpha[None, :]
+            T = A @ S
+            info.matvecs += s
+            tt = _cdot(T, T)
+            _denominators(tt)
+            omega = _cdot(T, S) / tt
+            X = X + P * alpha[None, :] + S * omega[None, :]
+            R = S - T * omega[None, :]
+            if hook:
+                hook(k + 1, X, {"omega": omega})
+            if _finish(info, _fro(R), nr0, tol, k + 1):
+                return X, info
+            rho_new = _cdot(Rt, R)
+            _denominators(rho)
+            _denominators(omega)
+            beta = (rho_new / rho) * (alpha / omega)
+            rho = rho_new
+            P = R + (P - V * omega[None, :]) * beta[None, :]
+    except _Breakdown:
+        info.status = STATUS_BREAKDOWN
+        info.breakdown_iter = info.iterations
+    return X, info
+
+
 METHODS = {
     "gl_bicg": gl_bicg,
     "egl_bicg": egl_bicg,
@@ -615,6 +746,8 @@ PIN_METHODS = {
     "bl_bicg": bl_bicg,
     "bl_bicgstab": bl_bicgstab,
     "li_bicg": li_bicg,
+    "li_qmr": li_qmr,
+    "li_bicgstab": li_bicgstab,
 }
 
 

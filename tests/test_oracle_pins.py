@@ -43,7 +43,7 @@ def _rel(a, b):
 # ---------------------------------------------------------------------------
 # P1: converged solutions agree with dense LU
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("method", list(O.METHODS))
+@pytest.mark.parametrize("method", list(O.METHODS) + list(O.PIN_METHODS))
 @pytest.mark.parametrize("kind", ["real", "complex"])
 def test_p1_dense_lu(method, kind):
     if kind == "real":
@@ -71,8 +71,8 @@ def _scipy_iterates(solver, A, b, kmax):
 
 FAMILY = {
     "bicg": (spla.bicg, ["gl_bicg", "egl_bicg", "bl_bicg", "bl_bicg_rq", "li_bicg"]),
-    "qmr": (spla.qmr, ["gl_qmr", "egl_qmr"]),
-    "bicgstab": (spla.bicgstab, ["gl_bicgstab", "bl_bicgstab", "bl_bicgstab_rq"]),
+    "qmr": (spla.qmr, ["gl_qmr", "egl_qmr", "li_qmr"]),
+    "bicgstab": (spla.bicgstab, ["gl_bicgstab", "bl_bicgstab", "bl_bicgstab_rq", "li_bicgstab"]),
 }
 
 
@@ -94,6 +94,28 @@ def test_p2_single_rhs_reduces_to_textbook(family, kind):
         it, _ = _iterates(fn, A, b, kmax)
         for k in range(1, kmax + 1):
             assert _rel(it[k], ref[k]) < 1e-9, (m, k, _rel(it[k], ref[k]))
+
+
+# ---------------------------------------------------------------------------
+# P2b: a loop-interchanged method is, column by column, the single-RHS method
+# on that column alone (Algorithm 1 and the prose of Section 2)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("family,method", [("bicg", "li_bicg"), ("qmr", "li_qmr"), ("bicgstab", "li_bicgstab")])
+@pytest.mark.parametrize("kind", ["real", "complex"])
+def test_p2b_loop_interchanged_is_columnwise_textbook(family, method, kind):
+    solver = FAMILY[family][0]
+    if kind == "real":
+        A = _small_real(10)
+        B = I.gaussian_block(A.shape[0], 3, seed=5)
+    else:
+        A = _small_complex(200)
+        B = I.gaussian_block(A.shape[0], 3, seed=5, complex_=True)
+    kmax = 10
+    it, _ = _iterates(O.PIN_METHODS[method], A, B, kmax)
+    for j in range(B.shape[1]):
+        ref = _scipy_iterates(solver, A, B[:, j], kmax)
+        for k in range(1, kmax + 1):
+            assert _rel(it[k][:, j:j + 1], ref[k]) < 1e-9, (method, j, k)
 
 
 # ---------------------------------------------------------------------------
