@@ -118,7 +118,7 @@ PAPER_TABLE2 = {
     "bl_bicgstab":    {1: (500, "0.093"), 2: (500, "div."), 3: (111, "2e-10")},
     "bl_bicgstab_rq": {1: (355, "1e-10"), 2: (500, "div."), 3: (101, "2e-10")},
 }
-ALL_METHODS = ("li_bicg", "gl_bicg", "egl_bicg", "gl_qmr", "egl_qmr", "gl_bicgstab",
+ALL_METHODS = ("li_bicg", "li_qmr", "li_bicgstab", "gl_bicg", "egl_bicg", "gl_qmr", "egl_qmr", "gl_bicgstab",
                "bl_bicg", "bl_bicg_rq", "bl_bicgstab", "bl_bicgstab_rq")
 
 

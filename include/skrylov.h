@@ -61,7 +61,9 @@ typedef enum {
     SKR_BL_BICGSTAB_RQ = 6,   /* Section 4, closing paragraph */
     SKR_BL_BICG = 7,          /* Algorithm 3 (block BiCG without QR of the residual) */
     SKR_BL_BICGSTAB = 8,      /* block BiCGStab of El Guennouni et al. (Sections 3 and 5.2) */
-    SKR_LI_BICG = 9           /* Algorithm 1 (loop-interchanged: s independent BiCG) */
+    SKR_LI_BICG = 9,          /* Algorithm 1 (loop-interchanged: s independent BiCG) */
+    SKR_LI_BICGSTAB = 10,     /* Section 2 (loop-interchanged: s independent BiCGStab) */
+    SKR_LI_QMR = 11           /* Section 2 (loop-interchanged: s independent QMR) */
 } skr_method;
 
 typedef enum { SKR_F64 = 0, SKR_C64 = 1 } skr_dtype;

@@ -21,7 +21,8 @@ SKR_NOT_CONVERGED, SKR_BREAKDOWN, SKR_DIVERGED = 1, 2, 3
 STATUS_NAMES = {0: "ok", 1: "not_converged", 2: "breakdown", 3: "diverged",
                 -1: "invalid", -2: "alloc", -3: "hip", -4: "unsupported"}
 METHODS = {"gl_bicg": 0, "egl_bicg": 1, "gl_qmr": 2, "egl_qmr": 3, "gl_bicgstab": 4,
-           "bl_bicg_rq": 5, "bl_bicgstab_rq": 6, "bl_bicg": 7, "bl_bicgstab": 8, "li_bicg": 9}
+           "bl_bicg_rq": 5, "bl_bicgstab_rq": 6, "bl_bicg": 7, "bl_bicgstab": 8, "li_bicg": 9,
+           "li_bicgstab": 10, "li_qmr": 11}
 SKR_F64, SKR_C64 = 0, 1
 SKR_MEM_HOST, SKR_MEM_DEVICE = 0, 1
 SKR_FMT_CSR, SKR_FMT_SELL = 0, 1

@@ -36,6 +36,10 @@ enum {
     M_T1, M_T1INV, M_T12, M_T2INV, M_T, M_T3INV,          // QR slot 1 work (M_T: R factor)
     M_N, M_A, M_AC, M_WC, M_B, M_RB, M_TMP,
     M_G1, M_RR, M_RHR, M_RT, M_W, M_MW,                   // plain Bl-BiCG / Bl-BiCGStab / Li-BiCG
+    // Li-QMR: per-column scalars on the diagonals, the identity and its negative
+    M_QRHO, M_QXI, M_QDELTA, M_QEPS, M_QBETA, M_QGAMMA, M_QTHETA, M_QETA, M_QF,
+    M_QRHON, M_QXIN, M_QDELTAN, M_QIRHO, M_QIXI, M_QMB, M_QMBC, M_QMCP, M_QMCQ,
+    M_QVV, M_QWW, M_QWV, M_ID, M_MID,
     M_COUNT
 };
 enum { SC_GAMMA = 40, SC_OMEGA = 41, SC_PIV = 48 };   // scalars / pivots inside sc[]

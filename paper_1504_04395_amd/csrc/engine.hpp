@@ -648,4 +648,137 @@ Method<T> make_bl_bicgstab(Env<T>& e, Arena& ar, T* rhs, T* x) {
     return m;
 }
 
+// Loop-interchanged BiCGStab: s independent BiCGStab recurrences (shadow
+// r~_c = r0_c), their products with A gathered into block products.  The
+// per-column alpha, omega and beta are diagonal s x s slots applied by the block
+// update kernels; the reductions are Gram diagonals.
+template <class T, int J>
+Method<T> make_li_bicgstab(Env<T>& e, Arena& ar, T* rhs, T* x) {
+    Method<T> m;
+    T* R = (T*)ar.take(e.blk_bytes());
+    T* Rt = (T*)ar.take(e.blk_bytes());
+    T* P = (T*)ar.take(e.blk_bytes());
+    T* V = (T*)ar.take(e.blk_bytes());
+    T* S = (T*)ar.take(e.blk_bytes());
+    T* Tm = (T*)ar.take(e.blk_bytes());
+    m.mv_per_iter = 2LL * e.s;
+    const int s = e.s, ss = s * s;
+    const Layout lt = tile_layout(e);
+    m.init = [=, &e]() {
+        k_copy<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, rhs, R, Rt, P);
+        k_fill0<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, x, nullptr, nullptr, nullptr);
+        k_flat_nrm_dot<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, R, nullptr, e.part);
+        k_init_ctl2<<<1, kScalar, 0, e.st>>>(e.ctl, e.hist, e.part, e.nb);
+        k_bl_gram<T, J><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.tl, Rt, R, e.part);    // rho = diag(R~^H R)
+        SKR_LAUNCHED();
+        reduce2(e, ss);
+        k_stash<<<1, kScalar, 0, e.st>>>(e.ctl, e.part2, e.p2, s, e.mats, M_N);
+        SKR_LAUNCHED();
+    };
+    m.iter = [=, &e]() {
+        spmm_j<T, J>(e, e.A, lt, P, V, EpiGram<T, J>{Rt, e.part}, e.ctl);           // V = A P, R~^H V
+        reduce2(e, ss);
+        k_lbs_alpha<<<1, kScalar, 0, e.st>>>(e.ctl, s, e.part2, e.p2, e.mats);
+        SKR_LAUNCHED();
+        axpm<T, J, false>(e, M_TMP, 0, R, V, nullptr, S);                           // S = R - V diag(alpha)
+        spmm_j<T, J>(e, e.A, lt, S, Tm, EpiGramOmega<T, J>{S, e.part}, e.ctl);      // T = A S, T^H S, T^H T
+        reduce2(e, 2 * ss);
+        k_lbs_omega<<<1, kScalar, 0, e.st>>>(e.ctl, s, e.part2, e.p2, e.mats);
+        SKR_LAUNCHED();
+        axpm<T, J, false>(e, M_A, 0, x, P, nullptr, x);                             // X += P diag(alpha)
+        axpm<T, J, false>(e, M_W, 0, x, S, nullptr, x);                             // X += S diag(omega)
+        axpm<T, J, true>(e, M_MW, 0, S, Tm, nullptr, R);                            // R = S - T diag(omega)
+        reduce2(e, ss);
+        k_stash<<<1, kScalar, 0, e.st>>>(e.ctl, e.part2, e.p2, s, e.mats, M_RR);
+        k_bl_gram<T, J><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.tl, Rt, R, e.part);     // rho' = diag(R~^H R)
+        SKR_LAUNCHED();
+        reduce2(e, ss);
+        k_lbs_beta<<<1, kScalar, 0, e.st>>>(e.ctl, e.hist, s, e.part2, e.p2, e.mats);
+        SKR_LAUNCHED();
+        axpm<T, J, false>(e, M_MW, 0, P, V, nullptr, P);                            // P -= V diag(omega)
+        axpm<T, J, false>(e, M_B, 0, R, P, nullptr, P);                             // P = R + P diag(beta)
+    };
+    return m;
+}
+
+// Loop-interchanged QMR: s independent QMR recurrences (the coupled two-term
+// form of the global variant, with per-column rho, xi, delta, eps, beta,
+// theta, gamma, eta), their products with A and A^H gathered into block
+// products.  Every per-column scaling is a diagonal slot applied by the block
+// update kernels, every per-column reduction a Gram diagonal.
+template <class T, int J>
+Method<T> make_li_qmr(Env<T>& e, Arena& ar, T* rhs, T* x) {
+    Method<T> m;
+    T* R = (T*)ar.take(e.blk_bytes());
+    T* V = (T*)ar.take(e.blk_bytes());
+    T* W = (T*)ar.take(e.blk_bytes());
+    T* P = (T*)ar.take(e.blk_bytes());
+    T* Qd = (T*)ar.take(e.blk_bytes());
+    T* Pt = (T*)ar.take(e.blk_bytes());
+    T* Zh = (T*)ar.take(e.blk_bytes());
+    T* D = (T*)ar.take(e.blk_bytes());
+    T* S = (T*)ar.take(e.blk_bytes());
+    m.mv_per_iter = 2LL * e.s;
+    const int s = e.s, ss = s * s;
+    const Layout lt = tile_layout(e);
+    auto gram = [=, &e](const T* Z, const T* Y, int slot) {   // mats[slot] = Z^H Y
+        k_bl_gram<T, J><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.tl, Z, Y, e.part);
+        SKR_LAUNCHED();
+        reduce2(e, ss);
+        k_stash<<<1, kScalar, 0, e.st>>>(e.ctl, e.part2, e.p2, s, e.mats, slot);
+        SKR_LAUNCHED();
+    };
+    auto stash = [=, &e](int slot) {
+        reduce2(e, ss);
+        k_stash<<<1, kScalar, 0, e.st>>>(e.ctl, e.part2, e.p2, s, e.mats, slot);
+        SKR_LAUNCHED();
+    };
+    // V = V diag(1/rho), W = W diag(1/xi), P = V - P diag(c_P), Qd = W - Qd diag(c_Q)
+    auto directions = [=, &e]() {
+        axpm<T, J, false>(e, M_QIRHO, 0, nullptr, V, nullptr, V);
+        axpm<T, J, false>(e, M_QIXI, 0, nullptr, W, nullptr, W);
+        axpm<T, J, false>(e, M_QMCP, 0, V, P, nullptr, P);
+        axpm<T, J, false>(e, M_QMCQ, 0, W, Qd, nullptr, Qd);
+    };
+    m.init = [=, &e]() {
+        k_copy<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, rhs, R, V, W);
+        k_fill0<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, x, D, S, P);
+        k_fill0<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, Qd, nullptr, nullptr, nullptr);
+        k_flat_nrm_dot<T><<<e.nb, kBlock, 0, e.st>>>(e.fl, R, nullptr, e.part);
+        k_init_ctl2<<<1, kScalar, 0, e.st>>>(e.ctl, e.hist, e.part, e.nb);
+        SKR_LAUNCHED();
+        gram(V, V, M_QVV);
+        gram(W, W, M_QWW);
+        gram(W, V, M_QWV);
+        k_lqmr_s0<<<1, kScalar, 0, e.st>>>(e.ctl, s, e.mats);
+        SKR_LAUNCHED();
+        directions();
+    };
+    m.iter = [=, &e]() {
+        spmm_j<T, J>(e, e.A, lt, P, Pt, EpiGram<T, J>{Qd, e.part}, e.ctl);         // Pt = A P, Qd^H Pt
+        reduce2(e, ss);
+        k_lqmr_s1<<<1, kScalar, 0, e.st>>>(e.ctl, s, e.part2, e.p2, e.mats);
+        SKR_LAUNCHED();
+        spmm_j<T, J>(e, e.AH, lt, Qd, Zh, EpiNone{}, e.ctl);                      // Zh = A^H Qd
+        axpm<T, J, true>(e, M_QMB, 0, Pt, V, nullptr, V);                          // Vt = Pt - V diag(beta)
+        stash(M_QVV);
+        axpm<T, J, true>(e, M_QMBC, 0, Zh, W, nullptr, W);                         // Wt = Zh - W diag(conj beta)
+        stash(M_QWW);
+        gram(W, V, M_QWV);
+        k_lqmr_s2<<<1, kScalar, 0, e.st>>>(e.ctl, s, e.mats);
+        SKR_LAUNCHED();
+        axpm<T, J, false>(e, M_QF, 0, nullptr, D, nullptr, D);                     // D = P diag(eta) + D diag(f)
+        axpm<T, J, false>(e, M_QETA, 0, D, P, nullptr, D);
+        axpm<T, J, false>(e, M_QF, 0, nullptr, S, nullptr, S);                     // S = Pt diag(eta) + S diag(f)
+        axpm<T, J, false>(e, M_QETA, 0, S, Pt, nullptr, S);
+        axpm<T, J, false>(e, M_ID, 0, x, D, nullptr, x);                           // X += D
+        axpm<T, J, true>(e, M_MID, 0, R, S, nullptr, R);                           // R -= S
+        stash(M_RR);
+        k_lqmr_s3<<<1, kScalar, 0, e.st>>>(e.ctl, e.hist, s, e.mats);
+        SKR_LAUNCHED();
+        directions();
+    };
+    return m;
+}
+
 }  // namespace skr

@@ -404,6 +404,8 @@ Method<T> make_method(int method, Env<T>& e, Arena& ar, T* rhs, T* x) {
         case SKR_BL_BICG: return make_bl_bicg<T, J>(e, ar, rhs, x, 0);
         case SKR_BL_BICGSTAB: return make_bl_bicgstab<T, J>(e, ar, rhs, x);
         case SKR_LI_BICG: return make_bl_bicg<T, J>(e, ar, rhs, x, 1);
+        case SKR_LI_BICGSTAB: return make_li_bicgstab<T, J>(e, ar, rhs, x);
+        case SKR_LI_QMR: return make_li_qmr<T, J>(e, ar, rhs, x);
     }
     throw Unsupported{"unknown method"};
 }
@@ -1004,7 +1006,7 @@ int skr_solve(skr_context* c, const skr_matrix* Mc, int32_t s, const void* B, in
     skr_matrix* M = const_cast<skr_matrix*>(Mc);
     if (s < 1 || s > kMaxS) return fail(c, SKR_E_INVALID, "s must be in [1, 32]");
     if (ldb < s || ldx < s) return fail(c, SKR_E_INVALID, "leading dimensions must be >= s");
-    if (method < SKR_GL_BICG || method > SKR_LI_BICG) return fail(c, SKR_E_INVALID, "unknown method");
+    if (method < SKR_GL_BICG || method > SKR_LI_QMR) return fail(c, SKR_E_INVALID, "unknown method");
     if (mem != SKR_MEM_HOST && mem != SKR_MEM_DEVICE) return fail(c, SKR_E_INVALID, "bad mem");
     skr_opts o;
     skr_opts_default(&o);

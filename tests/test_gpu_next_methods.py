@@ -1,6 +1,7 @@
 """GPU parity for the methods beyond the benchmark path: block BiCG
-(Algorithm 3), block BiCGStab (El Guennouni et al.) and loop-interchanged BiCG
-(Algorithm 1), against the oracle on the same seeded inputs, through the C ABI.
+(Algorithm 3), block BiCGStab (El Guennouni et al.), loop-interchanged BiCG
+(Algorithm 1) and loop-interchanged BiCGStab and QMR (Section 2), against the
+oracle on the same seeded inputs, through the C ABI.
 These plain block methods are the ones the QR variants stabilise (Section 5.2):
 on some inputs they break down or diverge, and then the status and the early
 iterates are what is compared."""
@@ -14,7 +15,7 @@ import oracle as O
 
 pytestmark = pytest.mark.gpu
 
-NEXT = ["bl_bicg", "bl_bicgstab", "li_bicg"]
+NEXT = ["bl_bicg", "bl_bicgstab", "li_bicg", "li_bicgstab", "li_qmr"]
 
 
 def say(*a):
