@@ -771,34 +771,48 @@ def _as_scipy(A):
 
 
 def solve(A, B, method: str, tol: float = 1e-8, maxit: int = 10000, preprocess: bool = True,
-          X0=None, shadow=None, hook=None) -> Result:
+          X0=None, shadow=None, hook=None, precond: str | None = None) -> Result:
     """Solve A X = B with one of the simultaneous methods.
 
     ``A``: scipy sparse matrix or ``inputs.CSR``; ``B``: n x s.  With
     ``preprocess`` the block of initial residuals R0 = B - A X0 is replaced by
     Q from R0 = Q R_R (Section 5), the method solves A D = Q and
-    X = X0 + D R_R is returned."""
+    X = X0 + D R_R is returned.  ``precond='ilu0'``: right no-fill ILU
+    preconditioning (``oracle.ilu``): the method runs on A M^-1 and
+    X = X0 + M^-1 D R_R."""
     A = _as_scipy(A)
     AH = A.conj().T.tocsr()
+    Aplain = A
+    M = None
+    if precond == "ilu0":
+        from .ilu import PrecOp, RightILU
+        M = RightILU(A)
+        A, AH = PrecOp(Aplain, AH, M, False), PrecOp(Aplain, AH, M, True)
+    elif precond is not None:
+        raise ValueError(precond)
     fn = METHODS.get(method) or PIN_METHODS[method]
     B = np.asarray(B)
-    dtype = np.result_type(A.dtype, B.dtype, np.float64)
+    dtype = np.result_type(Aplain.dtype, B.dtype, np.float64)
     B = B.astype(dtype)
     if X0 is None:
         X0 = np.zeros_like(B)
         R0 = B.copy()
     else:
         X0 = np.asarray(X0, dtype=dtype)
-        R0 = B - A @ X0
+        R0 = B - Aplain @ X0
     if preprocess:
         Qr, Rr = qr_pos(R0)
         D, info = fn(A, AH, Qr, tol, maxit, shadow, hook)
+        if M is not None:
+            D = M.minv(D)
         X = X0 + D @ Rr
     else:
         D, info = fn(A, AH, R0, tol, maxit, shadow, hook)
+        if M is not None:
+            D = M.minv(D)
         X = X0 + D
     nb = _fro(B)
-    rel_true = _fro(B - A @ X) / nb if nb > 0 else 0.0
+    rel_true = _fro(B - Aplain @ X) / nb if nb > 0 else 0.0
     status = info.status
     if status != STATUS_BREAKDOWN and rel_true > 1.0:
         status = STATUS_DIVERGED
