@@ -69,6 +69,7 @@ typedef enum {
 typedef enum { SKR_F64 = 0, SKR_C64 = 1 } skr_dtype;
 typedef enum { SKR_PREC_FP64 = 0, SKR_PREC_FP32_REFINE = 1 } skr_precision;
 typedef enum { SKR_MEM_HOST = 0, SKR_MEM_DEVICE = 1 } skr_mem;
+typedef enum { SKR_PRECOND_NONE = 0, SKR_PRECOND_ILU0 = 1 } skr_precond;
 typedef enum { SKR_FMT_CSR = 0, SKR_FMT_SELL = 1 } skr_format;
 
 typedef struct skr_context skr_context;
@@ -97,6 +98,11 @@ typedef struct {
     int32_t zero_x0;        /* ignore the contents of X on entry (X0 = 0)        [1]     */
     int32_t check_every;    /* host reads the device stop flag every m iterations [16]  */
     int32_t use_graph;      /* replay the m-iteration schedule as a hipGraph     [1]     */
+    int32_t precond;        /* skr_precond: SKR_PRECOND_ILU0 = right no-fill ILU
+                             * (Section 5.2): the method runs on A M^-1 with
+                             * M = L U from skr_matrix_ilu0 and returns
+                             * X = X0 + M^-1 D; residuals stay those of A X = B.
+                             * FP64, non-adjoint solves only                 [NONE]  */
 } skr_opts;
 
 /* Result record.  history is caller-owned (may be NULL).  FP64 solves: on
@@ -160,6 +166,25 @@ int skr_solve(skr_context* ctx, const skr_matrix* A, int32_t s, const void* B, i
  * uses.  X and Y in `mem`. */
 int skr_spmm(skr_context* ctx, const skr_matrix* A, int32_t s, const void* X, int64_t ldx,
              void* Y, int64_t ldy, int32_t mem, int32_t adjoint);
+
+/* Right no-fill ILU preconditioner (Section 5.2 preconditions Examples 1-3
+ * with it): A = L U - E with L unit lower and U upper triangular on A's
+ * sparsity pattern and (L U)_ij = a_ij there (ILU(0), row-wise elimination
+ * that drops every update outside the pattern).  Factored on the host from A's
+ * current values, then L, U, U^H and L^H go to device memory with their rows
+ * grouped into dependency levels for the triangular solves.  The factors stay
+ * with A until skr_matrix_update_values (which drops them) or destroy; calling
+ * this again refactors.  Needs every diagonal entry stored; a missing diagonal
+ * or a zero pivot returns SKR_E_INVALID and leaves A without factors. */
+int skr_matrix_ilu0(skr_context* ctx, skr_matrix* A);
+
+/* Y = M^-1 Z (adjoint = 0) or Y = M^-H Z (adjoint = 1), M = L U from
+ * skr_matrix_ilu0: two level-scheduled triangular solves over an n x s block,
+ * rows row-major with leading dimensions ldz, ldy, both in `mem`.  Z and Y may
+ * be the same device block when ldz = ldy = s.  SKR_E_INVALID when A has no
+ * factors. */
+int skr_precond_apply(skr_context* ctx, const skr_matrix* A, int32_t s, const void* Z, int64_t ldz,
+                      void* Y, int64_t ldy, int32_t mem, int32_t adjoint);
 
 /* Sampled dense-dense product on A's pattern (the gradient with respect to A's
  * stored values of X = A^{-1} B is this with G = A^{-H} dL/dX and scale = -1):

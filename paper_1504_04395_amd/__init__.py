@@ -7,8 +7,8 @@ arithmetic runs in the HIP library ``libskrylov.so`` behind the C ABI of
 ``include/skrylov.h``; this package is its ctypes binding.
 """
 from ._binding import (  # noqa: F401
-    LIB_PATH, METHODS, PRECISIONS, STATUS_NAMES, Context, Matrix, SkrError, SolveInfo, block_qr, load_library,
-    opts_default, sddmm, solve, spmm,
+    LIB_PATH, METHODS, PRECISIONS, PRECONDS, STATUS_NAMES, Context, Matrix, SkrError, SolveInfo, block_qr,
+    load_library, opts_default, precond_apply, sddmm, solve, spmm,
 )
 
 

@@ -20,6 +20,7 @@ SKR_OK, SKR_E_INVALID, SKR_E_ALLOC, SKR_E_HIP, SKR_E_UNSUPPORTED = 0, -1, -2, -3
 SKR_NOT_CONVERGED, SKR_BREAKDOWN, SKR_DIVERGED = 1, 2, 3
 STATUS_NAMES = {0: "ok", 1: "not_converged", 2: "breakdown", 3: "diverged",
                 -1: "invalid", -2: "alloc", -3: "hip", -4: "unsupported"}
+PRECONDS = {None: 0, "none": 0, "ilu0": 1}
 METHODS = {"gl_bicg": 0, "egl_bicg": 1, "gl_qmr": 2, "egl_qmr": 3, "gl_bicgstab": 4,
            "bl_bicg_rq": 5, "bl_bicgstab_rq": 6, "bl_bicg": 7, "bl_bicgstab": 8, "li_bicg": 9,
            "li_bicgstab": 10, "li_qmr": 11}
@@ -32,7 +33,8 @@ PRECISIONS = {"fp64": 0, "fp32_refine": 1}
 class skr_opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int32), ("preprocess_qr", ctypes.c_int32),
-                ("zero_x0", ctypes.c_int32), ("check_every", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+                ("zero_x0", ctypes.c_int32), ("check_every", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("precond", ctypes.c_int32)]
 
 
 class skr_result(ctypes.Structure):
@@ -65,6 +67,9 @@ _SIGS = {
     "skr_spmm": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, _VP, ctypes.c_int64, _VP, ctypes.c_int64, ctypes.c_int32,
                                 ctypes.c_int32]),
     "skr_sddmm": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int32]),
+    "skr_matrix_ilu0": (ctypes.c_int, [_VP, _VP]),
+    "skr_precond_apply": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, _VP, ctypes.c_int64, _VP, ctypes.c_int64,
+                                         ctypes.c_int32, ctypes.c_int32]),
     "skr_block_qr": (ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _VP, _VP,
                                     ctypes.POINTER(ctypes.c_double), ctypes.c_int32]),
 }
@@ -209,6 +214,12 @@ class Matrix:
         p, mem, _, keep = _ptr_mem(data)
         _check(self.ctx, load_library().skr_matrix_update_values(self.handle, _VP(p), mem))
 
+    def ilu0(self):
+        """skr_matrix_ilu0: attach right no-fill ILU factors (used by solves with
+        precond='ilu0' until the values change)."""
+        _check(self.ctx, load_library().skr_matrix_ilu0(self.ctx.handle, self.handle))
+        return self
+
     @property
     def sell_padding(self) -> float:
         return load_library().skr_matrix_sell_padding(self.handle)
@@ -251,10 +262,12 @@ def opts_default() -> skr_opts:
 def solve(ctx: Context, A: Matrix, B, method: str, X=None, x0_zero: bool = False, tol: float = 1e-8,
           maxit: int = 10000,
           precision: str = "fp64", inner_tol: float = 1e-4, max_outer: int = 10, preprocess_qr: bool = True,
-          check_every: int = 16, use_graph: bool = True, adjoint: bool = False, history_cap: int | None = None):
+          check_every: int = 16, use_graph: bool = True, adjoint: bool = False, history_cap: int | None = None,
+          precond: str | None = None):
     """skr_solve.  B: n x s (numpy or torch CUDA tensor).  X: optional initial
     guess / output array of the same kind (a new one is created if None);
-    with x0_zero the contents of X are ignored (X0 = 0).  Returns (X, SolveInfo)."""
+    with x0_zero the contents of X are ignored (X0 = 0).  precond='ilu0':
+    right ILU(0) preconditioning (A.ilu0() first).  Returns (X, SolveInfo)."""
     lib = load_library()
     pB, memB, dt, keepB = _ptr_mem(B)
     if dt != A.dtype:
@@ -285,6 +298,7 @@ def solve(ctx: Context, A: Matrix, B, method: str, X=None, x0_zero: bool = False
     o.zero_x0 = zero_x0
     o.check_every = check_every
     o.use_graph = int(use_graph)
+    o.precond = PRECONDS[precond]
     cap = history_cap if history_cap is not None else maxit + 2
     hist = np.zeros(max(cap, 1), dtype=np.float64)
     r = skr_result()
@@ -316,6 +330,23 @@ def spmm(ctx: Context, A: Matrix, X, Y=None, adjoint: bool = False, sync: bool =
     if sync and mem == SKR_MEM_DEVICE:
         import torch
         torch.cuda.synchronize()
+    return Y
+
+
+def precond_apply(ctx: Context, A: Matrix, Z, Y=None, adjoint: bool = False):
+    """skr_precond_apply: Y = M^-1 Z (or M^-H Z) with A's ILU(0) factors."""
+    pZ, mem, dt, keep = _ptr_mem(Z)
+    n, s = Z.shape
+    if Y is None:
+        if _is_torch(Z):
+            import torch
+            Y = torch.empty_like(Z)
+        else:
+            Y = np.empty_like(keep)
+    pY, _, _, _ = _ptr_mem(Y)
+    _order_torch(Z, Y)
+    _check(ctx, load_library().skr_precond_apply(ctx.handle, A.handle, s, _VP(pZ), s, _VP(pY), s, mem,
+                                                 int(adjoint)))
     return Y
 
 

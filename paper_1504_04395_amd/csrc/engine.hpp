@@ -17,6 +17,7 @@
 #include "blk.hpp"
 #include "common.hpp"
 #include "glk.hpp"
+#include "ilu.hpp"
 #include "pln.hpp"
 #include "spmm.hpp"
 
@@ -78,8 +79,34 @@ struct Env {
     c64* mats = nullptr;
     Operand<T> A, AH;
     int J = 1;               // ceil(s/16)
+    // right preconditioning M = L U: while pc_on, products with A become
+    // A M^-1 and products with A^H become M^-H A^H (pc_tmp: one n x s block)
+    const Ilu* pc = nullptr;
+    bool pc_on = false;
+    T* pc_tmp = nullptr;
     size_t blk_bytes() const { return (size_t)n * s * sizeof(T); }
 };
+
+template <class T>
+constexpr bool kFp64 = std::is_same<T, double>::value || std::is_same<T, c64>::value;
+
+// Y = M^-1 Z (adj: M^-H Z) with M = L U; Y may equal Z.
+template <class T>
+void prec_apply(Env<T>& e, int s, const T* Z, T* Y, bool adj, const Ctl* ctl) {
+    if constexpr (kFp64<T>) {
+        const Ilu& p = *e.pc;
+        if (!adj) {
+            tri_solve<T>(e.st, p.L, s, Z, Y, ctl);
+            tri_solve<T>(e.st, p.U, s, Y, Y, ctl);
+        } else {
+            tri_solve<T>(e.st, p.UH, s, Z, Y, ctl);
+            tri_solve<T>(e.st, p.LH, s, Y, Y, ctl);
+        }
+        SKR_LAUNCHED();
+    } else {
+        throw Unsupported{"preconditioning needs FP64 data"};
+    }
+}
 
 inline int ilog2(int v) {
     int l = 0;
@@ -112,6 +139,24 @@ void env_layout(Env<T>& e, int n, int s) {
 // ------------------------------------------------------------------ launch helpers
 template <class T, int J, class Epi, int J16 = (J == 1 ? 1 : 2)>
 void spmm_j(Env<T>& e, const Operand<T>& op, const Layout& ly, const T* X, T* Y, Epi epi, const Ctl* ctl) {
+    if (e.pc_on) {
+        e.pc_on = false;
+        if (&op == &e.A) {                                   // Y = A (M^-1 X), epilogue on Y
+            prec_apply(e, ly.s, X, e.pc_tmp, false, ctl);
+            spmm_j<T, J, Epi, J16>(e, op, ly, e.pc_tmp, Y, epi, ctl);
+        } else {                                             // Y = M^-H (A^H X), epilogue after
+            spmm_j<T, J, EpiNone, J16>(e, op, ly, X, e.pc_tmp, EpiNone{}, ctl);
+            prec_apply(e, ly.s, e.pc_tmp, Y, true, ctl);
+            if constexpr (std::is_same<Epi, EpiGram<T, J>>::value) {
+                k_bl_gram<T, J><<<e.nb, kBlock, 0, e.st>>>(ctl, e.tl, epi.Z, Y, epi.part);   // Z^H Y
+                SKR_LAUNCHED();
+            } else if constexpr (!std::is_same<Epi, EpiNone>::value) {
+                throw Unsupported{"epilogue not available on the preconditioned adjoint product"};
+            }
+        }
+        e.pc_on = true;
+        return;
+    }
     if (op.sell) {
         int nchunks = (e.n + op.sl.C - 1) / op.sl.C;
         int cpb = (nchunks + e.nb - 1) / e.nb;
@@ -149,6 +194,20 @@ void spmm_j(Env<T>& e, const Operand<T>& op, const Layout& ly, const T* X, T* Y,
 }
 template <class T, class Epi>
 void spmm(Env<T>& e, const Operand<T>& op, const Layout& ly, const T* X, T* Y, Epi epi, const Ctl* ctl) {
+    if (e.pc_on) {
+        e.pc_on = false;
+        if (&op == &e.A) {                                   // Y = A (M^-1 X), epilogue on Y
+            prec_apply(e, ly.s, X, e.pc_tmp, false, ctl);
+            spmm(e, op, ly, e.pc_tmp, Y, epi, ctl);
+        } else {                                             // Y = M^-H (A^H X)
+            if constexpr (!std::is_same<Epi, EpiNone>::value)
+                throw Unsupported{"epilogue not available on the preconditioned adjoint product"};
+            spmm(e, op, ly, X, e.pc_tmp, EpiNone{}, ctl);
+            prec_apply(e, ly.s, e.pc_tmp, Y, true, ctl);
+        }
+        e.pc_on = true;
+        return;
+    }
     if constexpr (std::is_same<Epi, EpiNone>::value) {
         if (ly.s == 1 && !op.sell) {   // single vector: 8 lanes per row
             const int per_xcd = ((e.n + 7) / 8 + 31) / 32 * 32;

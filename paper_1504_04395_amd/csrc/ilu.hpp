@@ -1,0 +1,184 @@
+// Right no-fill ILU preconditioning (Section 5.2 uses a right ILU without fill
+// for Examples 1-3).
+//
+// Set-up (host, once per matrix): ILU(0) by row-wise Gaussian elimination that
+// keeps only updates inside A's sparsity pattern (Saad, Section 10.3.2), so
+// that (L U)_ij = a_ij on the pattern; L is unit lower, U upper triangular.
+// The four triangular operators a right-preconditioned method needs --
+// L and U for A M^-1, U^H and L^H for M^-H A^H -- are stored as CSR of their
+// strictly triangular parts plus the diagonal, with their rows grouped into
+// dependency levels: the rows of one level depend only on earlier levels.
+//
+// Apply (device): one launch per level; thread (row, column) of the n x s
+// block computes y_i = (z_i - sum_j t_ij y_j) [/ t_ii].  A level's rows read
+// only rows of earlier levels, so in-place solves (Y == Z) are race-free.
+#pragma once
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+namespace skr {
+
+struct IluError {
+    std::string what;
+};
+
+template <class T>
+struct TriOp {
+    const int* rp;     // strictly triangular part, CSR
+    const int* ci;
+    const T* va;
+    const T* dg;       // diagonal; nullptr = unit diagonal
+    const int* rows;   // rows ordered by level
+};
+
+__device__ inline double tdiv(double a, double b) { return a / b; }
+__device__ inline c64 tdiv(c64 a, c64 b) { return cdiv(a, b); }
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_trsv_level(const Ctl* ctl, TriOp<T> F, int l0, int cnt, int s,
+                                                       const T* Z, T* Y) {
+    if (stopped(ctl)) return;
+    const long long g = (long long)blockIdx.x * kBlock + threadIdx.x;
+    const int q = (int)(g / s);
+    if (q >= cnt) return;
+    const int c = (int)(g - (long long)q * s);
+    const int i = F.rows[l0 + q];
+    T acc = Z[(size_t)i * s + c];
+    for (int k = F.rp[i]; k < F.rp[i + 1]; ++k) acc = fma_(-F.va[k], Y[(size_t)F.ci[k] * s + c], acc);
+    Y[(size_t)i * s + c] = F.dg ? tdiv(acc, F.dg[i]) : acc;
+}
+
+// ------------------------------------------------------------------ host side
+inline bool hzero(double v) { return v == 0.0; }
+inline bool hzero(c64 v) { return v.x == 0.0 && v.y == 0.0; }
+inline bool hfinite(double v) { return std::isfinite(v); }
+inline bool hfinite(c64 v) { return std::isfinite(v.x) && std::isfinite(v.y); }
+inline double hdiv(double a, double b) { return a / b; }
+inline c64 hdiv(c64 a, c64 b) { return cdiv(a, b); }
+inline double hconj(double a) { return a; }
+inline c64 hconj(c64 a) { return conj_(a); }
+
+// One triangular operator: host arrays while building, device arrays after upload.
+template <class T>
+struct TriHost {
+    std::vector<int> rp, ci, rows, lvl;
+    std::vector<T> va, dg;
+};
+
+struct TriDev {
+    int *rp = nullptr, *ci = nullptr, *rows = nullptr;
+    void *va = nullptr, *dg = nullptr;
+    std::vector<int> lvl;   // level offsets into rows (host copy, drives the launches)
+    size_t bytes = 0;
+};
+
+struct Ilu {
+    int dtype = 0;
+    TriDev L, U, UH, LH;
+};
+
+// Level of each row: forward (lower operators, row i needs rows j < i) or
+// backward (upper operators, row i needs rows j > i); rows sorted by level.
+template <class T>
+void tri_levels(TriHost<T>& t, int n, bool forward) {
+    std::vector<int> lev(n, 0);
+    int nlev = 0;
+    for (int q = 0; q < n; ++q) {
+        const int i = forward ? q : n - 1 - q;
+        int l = 0;
+        for (int k = t.rp[i]; k < t.rp[i + 1]; ++k) l = std::max(l, lev[t.ci[k]] + 1);
+        lev[i] = l;
+        nlev = std::max(nlev, l + 1);
+    }
+    t.lvl.assign(nlev + 1, 0);
+    for (int i = 0; i < n; ++i) ++t.lvl[lev[i] + 1];
+    for (int l = 0; l < nlev; ++l) t.lvl[l + 1] += t.lvl[l];
+    std::vector<int> fill(t.lvl.begin(), t.lvl.end() - 1);
+    t.rows.assign(n, 0);
+    for (int i = 0; i < n; ++i) t.rows[fill[lev[i]]++] = i;
+}
+
+// Conjugate transpose of a strictly triangular CSR (counting sort by column).
+template <class T>
+void tri_adjoint(const TriHost<T>& a, int n, TriHost<T>& out) {
+    const int nnz = a.rp[n];
+    out.rp.assign(n + 1, 0);
+    for (int k = 0; k < nnz; ++k) ++out.rp[a.ci[k] + 1];
+    for (int i = 0; i < n; ++i) out.rp[i + 1] += out.rp[i];
+    std::vector<int> fill(out.rp.begin(), out.rp.end() - 1);
+    out.ci.assign(nnz, 0);
+    out.va.assign(nnz, T{});
+    for (int i = 0; i < n; ++i)
+        for (int k = a.rp[i]; k < a.rp[i + 1]; ++k) {
+            const int d = fill[a.ci[k]]++;
+            out.ci[d] = i;
+            out.va[d] = hconj(a.va[k]);
+        }
+    if (!a.dg.empty()) {
+        out.dg.resize(n);
+        for (int i = 0; i < n; ++i) out.dg[i] = hconj(a.dg[i]);
+    }
+}
+
+// ILU(0) of the CSR (rp, ci sorted within rows, a) into L (strict lower, unit
+// diagonal) and U (strict upper + diagonal).  Throws IluError for a missing
+// diagonal entry or a zero / non-finite pivot.
+template <class T>
+void ilu0_factor(int n, const std::vector<int>& rp, const std::vector<int>& ci, std::vector<T> a, TriHost<T>& L,
+                 TriHost<T>& U) {
+    std::vector<int> dpos(n, -1), pos(n, -1);
+    for (int i = 0; i < n; ++i)
+        for (int k = rp[i]; k < rp[i + 1]; ++k)
+            if (ci[k] == i) dpos[i] = k;
+    for (int i = 0; i < n; ++i)
+        if (dpos[i] < 0) throw IluError{"ILU(0): row " + std::to_string(i) + " has no diagonal entry"};
+    for (int i = 0; i < n; ++i) {
+        for (int k = rp[i]; k < rp[i + 1]; ++k) pos[ci[k]] = k;
+        for (int e = rp[i]; e < rp[i + 1] && ci[e] < i; ++e) {
+            const int kk = ci[e];
+            const T lik = hdiv(a[e], a[dpos[kk]]);
+            a[e] = lik;
+            for (int f = dpos[kk] + 1; f < rp[kk + 1]; ++f)
+                if (pos[ci[f]] >= 0) a[pos[ci[f]]] = a[pos[ci[f]]] - lik * a[f];
+        }
+        if (hzero(a[dpos[i]]) || !hfinite(a[dpos[i]]))
+            throw IluError{"ILU(0): zero or non-finite pivot in row " + std::to_string(i)};
+        for (int k = rp[i]; k < rp[i + 1]; ++k) pos[ci[k]] = -1;
+    }
+    L.rp.assign(n + 1, 0);
+    U.rp.assign(n + 1, 0);
+    U.dg.resize(n);
+    for (int i = 0; i < n; ++i) {
+        for (int k = rp[i]; k < rp[i + 1]; ++k) {
+            if (ci[k] < i) {
+                L.ci.push_back(ci[k]);
+                L.va.push_back(a[k]);
+            } else if (ci[k] > i) {
+                U.ci.push_back(ci[k]);
+                U.va.push_back(a[k]);
+            }
+        }
+        U.dg[i] = a[dpos[i]];
+        L.rp[i + 1] = (int)L.ci.size();
+        U.rp[i + 1] = (int)U.ci.size();
+    }
+}
+
+// Y = T^-1 Z for one triangular operator, level by level (Y may equal Z).
+template <class T>
+void tri_solve(hipStream_t st, const TriDev& t, int s, const T* Z, T* Y, const Ctl* ctl) {
+    const TriOp<T> op{t.rp, t.ci, (const T*)t.va, (const T*)t.dg, t.rows};
+    for (size_t l = 0; l + 1 < t.lvl.size(); ++l) {
+        const int l0 = t.lvl[l], cnt = t.lvl[l + 1] - l0;
+        const long long threads = (long long)cnt * s;
+        const int grid = (int)((threads + kBlock - 1) / kBlock);
+        k_trsv_level<T><<<grid, kBlock, 0, st>>>(ctl, op, l0, cnt, s, Z, Y);
+    }
+}
+
+}  // namespace skr

@@ -190,6 +190,7 @@ struct skr_matrix {
     bool sell = false;
     DevSell SA, SAH;
     double sell_pad = 0.0;
+    Ilu* ilu = nullptr;   // right ILU(0) factors (skr_matrix_ilu0), dropped when the values change
 };
 
 namespace {
@@ -287,6 +288,76 @@ void upload_sell(DevSell& d, const HostSell& h, int C, int sigma, int n) {
         SKR_HIP(hipMemcpy(d.ci, h.ci.data(), d.slots * sizeof(int), hipMemcpyHostToDevice));
         SKR_HIP(hipMemcpy(d.idx, h.idx.data(), d.slots * sizeof(int), hipMemcpyHostToDevice));
     }
+}
+
+void free_tri(TriDev& t) {
+    void* ps[] = {t.rp, t.ci, t.rows, t.va, t.dg};
+    for (void* p : ps)
+        if (p) (void)hipFree(p);
+    t = TriDev{};
+}
+
+void free_ilu(skr_matrix* M) {
+    if (!M->ilu) return;
+    free_tri(M->ilu->L);
+    free_tri(M->ilu->U);
+    free_tri(M->ilu->UH);
+    free_tri(M->ilu->LH);
+    delete M->ilu;
+    M->ilu = nullptr;
+}
+
+template <class T>
+void upload_tri(const TriHost<T>& h, int n, TriDev& d, hipStream_t st) {
+    auto up = [&](void** dst, const void* src, size_t bytes) {
+        SKR_HIP(hipMalloc(dst, std::max<size_t>(bytes, 1)));
+        if (bytes) SKR_HIP(hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, st));
+        d.bytes += bytes;
+    };
+    up((void**)&d.rp, h.rp.data(), sizeof(int) * (n + 1));
+    up((void**)&d.ci, h.ci.data(), sizeof(int) * h.ci.size());
+    up((void**)&d.rows, h.rows.data(), sizeof(int) * n);
+    up(&d.va, h.va.data(), sizeof(T) * h.va.size());
+    if (!h.dg.empty()) up(&d.dg, h.dg.data(), sizeof(T) * n);
+    d.lvl = h.lvl;
+}
+
+// ILU(0) on the host from the device CSR, level schedules, upload of L, U, U^H, L^H.
+template <class T>
+void build_ilu(skr_matrix* M, hipStream_t st) {
+    const int n = M->n, nnz = M->nnz;
+    std::vector<int> rp(n + 1), ci(nnz);
+    std::vector<T> va(nnz);
+    SKR_HIP(hipMemcpyAsync(rp.data(), M->rp, sizeof(int) * (n + 1), hipMemcpyDeviceToHost, st));
+    if (nnz) {
+        SKR_HIP(hipMemcpyAsync(ci.data(), M->ci, sizeof(int) * nnz, hipMemcpyDeviceToHost, st));
+        SKR_HIP(hipMemcpyAsync(va.data(), M->va, sizeof(T) * nnz, hipMemcpyDeviceToHost, st));
+    }
+    SKR_HIP(hipStreamSynchronize(st));
+    TriHost<T> L, U, UH, LH;
+    ilu0_factor<T>(n, rp, ci, std::move(va), L, U);
+    tri_adjoint(U, n, UH);
+    tri_adjoint(L, n, LH);
+    tri_levels(L, n, true);
+    tri_levels(U, n, false);
+    tri_levels(UH, n, true);
+    tri_levels(LH, n, false);
+    std::unique_ptr<Ilu> p(new Ilu);
+    p->dtype = M->dtype;
+    try {
+        upload_tri(L, n, p->L, st);
+        upload_tri(U, n, p->U, st);
+        upload_tri(UH, n, p->UH, st);
+        upload_tri(LH, n, p->LH, st);
+        SKR_HIP(hipStreamSynchronize(st));
+    } catch (...) {
+        free_tri(p->L);
+        free_tri(p->U);
+        free_tri(p->UH);
+        free_tri(p->LH);
+        throw;
+    }
+    M->ilu = p.release();
 }
 
 void free_sell(DevSell& d) {
@@ -538,11 +609,17 @@ int solve_fp64(skr_context* c, const skr_matrix* M, int s, const T* B, T* X, boo
     e.st = c->stream();
     e.A = operand<T>(M, adjoint != 0, false);
     e.AH = operand<T>(M, adjoint == 0, false);
+    if (o.precond == SKR_PRECOND_ILU0) {
+        if (!M->ilu) throw Unsupported{"ILU(0) preconditioning requested: call skr_matrix_ilu0 first"};
+        if (adjoint) throw Unsupported{"ILU(0) preconditioning of adjoint solves is not available"};
+        e.pc = M->ilu;
+    }
     auto carve = [&](Arena& ar, T** rhs, T** D, T** tmp, Method<T>* m) {
         take_common(e, ar, o.maxit);
         *rhs = (T*)ar.take(e.blk_bytes());
         *D = (T*)ar.take(e.blk_bytes());
         *tmp = (T*)ar.take(e.blk_bytes());
+        if (e.pc) e.pc_tmp = (T*)ar.take(e.blk_bytes());
         *m = make_method<T, J>(method, e, ar, *rhs, *D);
     };
     T *rhs, *D, *tmp;
@@ -571,8 +648,14 @@ int solve_fp64(skr_context* c, const skr_matrix* M, int s, const T* B, T* X, boo
         res->breakdown_iter = 0;
         return SKR_BREAKDOWN;
     }
+    e.pc_on = e.pc != nullptr;
     InnerStats st = iterate<T>(c, e, m, method, o.tol, o.maxit, o.check_every, o.use_graph != 0,
-                               fnv(&ar, sizeof(ar), 0));
+                               fnv(&e.pc, sizeof(e.pc), fnv(&ar, sizeof(ar), 0)));
+    e.pc_on = false;
+    if (e.pc) {   // the method solved A M^-1 D = Q: the correction is M^-1 D
+        prec_apply(e, s, D, e.pc_tmp, false, nullptr);
+        D = e.pc_tmp;
+    }
     // X = X0 + D R_R  (or X0 + D)
     k_xupd<T, T, J><<<e.nb, kBlock, mat_lds(s, 1, 1), e.st>>>(e.tl, e.mats, pre ? M_RB : -1, X, D, 0);
     SKR_LAUNCHED();
@@ -756,6 +839,8 @@ template <class T>
 int solve_dispatch(skr_context* c, skr_matrix* M, int s, const T* B, T* X, bool x0zero, int method,
                    const skr_opts& o, int adjoint, skr_result* res) {
     const bool mixed = o.precision == SKR_PREC_FP32_REFINE;
+    if (mixed && o.precond != SKR_PRECOND_NONE)
+        throw Unsupported{"ILU(0) preconditioning is available for FP64 solves only"};
     if (s <= 16) {
         return mixed ? solve_mixed<T, 1>(c, M, s, B, X, x0zero, method, o, adjoint, res)
                      : solve_fp64<T, 1>(c, M, s, B, X, x0zero, method, o, adjoint, res);
@@ -779,6 +864,8 @@ int guarded(skr_context* c, F&& f) {
         return fail(c, SKR_E_ALLOC, "device or host memory allocation failed");
     } catch (const Unsupported& u) {
         return fail(c, SKR_E_UNSUPPORTED, u.what);
+    } catch (const IluError& u) {
+        return fail(c, SKR_E_INVALID, u.what);
     } catch (...) {
         return fail(c, SKR_E_INVALID, "unexpected error");
     }
@@ -798,6 +885,7 @@ void skr_opts_default(skr_opts* o) {
     o->max_outer = 10;
     o->preprocess_qr = 1;
     o->zero_x0 = 1;
+    o->precond = SKR_PRECOND_NONE;
     o->check_every = 16;
     o->use_graph = 1;
 }
@@ -970,6 +1058,10 @@ int skr_matrix_update_values(skr_matrix* M, const void* values, int32_t mem) {
                                    c->stream()));
         refresh_values(M, c->stream());
         SKR_HIP(hipStreamSynchronize(c->stream()));
+        if (M->ilu) {   // the factors belong to the old values
+            invalidate_graphs(c);
+            free_ilu(M);
+        }
         return SKR_OK;
     });
 }
@@ -992,6 +1084,7 @@ int skr_matrix_destroy(skr_matrix* M) {
         free_sell(M->SA);
         free_sell(M->SAH);
     }
+    free_ilu(M);
     delete M;
     return SKR_OK;
 }
@@ -1015,6 +1108,8 @@ int skr_solve(skr_context* c, const skr_matrix* Mc, int32_t s, const void* B, in
         return fail(c, SKR_E_INVALID, "bad options");
     if (o.precision != SKR_PREC_FP64 && o.precision != SKR_PREC_FP32_REFINE)
         return fail(c, SKR_E_INVALID, "bad precision");
+    if (o.precond != SKR_PRECOND_NONE && o.precond != SKR_PRECOND_ILU0)
+        return fail(c, SKR_E_INVALID, "bad precond");
     double* hist = res->history;
     int cap = res->history_cap;
     std::memset(res, 0, sizeof(*res));
@@ -1107,6 +1202,67 @@ int skr_spmm(skr_context* c, const skr_matrix* M, int32_t s, const void* X, int6
             SKR_HIP(hipStreamSynchronize(st));
             (void)hipFree(Xd);
             (void)hipFree(Yd);
+        }
+        return SKR_OK;
+    });
+}
+
+int skr_matrix_ilu0(skr_context* c, skr_matrix* M) {
+    if (!c) return SKR_E_INVALID;
+    if (!M) return fail(c, SKR_E_INVALID, "null argument");
+    return guarded(c, [&]() -> int {
+        SKR_HIP(hipSetDevice(c->device));
+        hipStream_t st = c->stream();
+        SKR_HIP(hipStreamSynchronize(st));
+        invalidate_graphs(c);
+        free_ilu(M);
+        if (M->dtype == SKR_C64) build_ilu<c64>(M, st);
+        else build_ilu<double>(M, st);
+        return SKR_OK;
+    });
+}
+
+int skr_precond_apply(skr_context* c, const skr_matrix* M, int32_t s, const void* Z, int64_t ldz, void* Y,
+                      int64_t ldy, int32_t mem, int32_t adjoint) {
+    if (!c) return SKR_E_INVALID;
+    if (!M || !Z || !Y) return fail(c, SKR_E_INVALID, "null argument");
+    if (!M->ilu) return fail(c, SKR_E_INVALID, "no ILU(0) factors: call skr_matrix_ilu0 first");
+    if (s < 1 || s > kMaxS || ldz < s || ldy < s) return fail(c, SKR_E_INVALID, "bad s or leading dimension");
+    return guarded(c, [&]() -> int {
+        SKR_HIP(hipSetDevice(c->device));
+        const int n = M->n;
+        const size_t es = elt(M->dtype, false);
+        const size_t bytes = (size_t)n * s * es;
+        hipStream_t st = c->stream();
+        const bool direct = mem == SKR_MEM_DEVICE && ldz == s && ldy == s;
+        void *Zd = (void*)Z, *Yd = Y;
+        if (!direct) {
+            SKR_HIP(hipMalloc(&Zd, std::max<size_t>(bytes, 1)));
+            SKR_HIP(hipMalloc(&Yd, std::max<size_t>(bytes, 1)));
+            SKR_HIP(hipMemcpy2DAsync(Zd, s * es, Z, ldz * es, s * es, n,
+                                     mem == SKR_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, st));
+        }
+        if (M->dtype == SKR_C64) {
+            Env<c64> e;
+            env_layout(e, n, s);
+            e.st = st;
+            e.pc = M->ilu;
+            prec_apply(e, s, (const c64*)Zd, (c64*)Yd, adjoint != 0, nullptr);
+        } else {
+            Env<double> e;
+            env_layout(e, n, s);
+            e.st = st;
+            e.pc = M->ilu;
+            prec_apply(e, s, (const double*)Zd, (double*)Yd, adjoint != 0, nullptr);
+        }
+        if (!direct) {
+            SKR_HIP(hipMemcpy2DAsync(Y, ldy * es, Yd, s * es, s * es, n,
+                                     mem == SKR_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st));
+            SKR_HIP(hipStreamSynchronize(st));
+            (void)hipFree(Zd);
+            (void)hipFree(Yd);
+        } else {
+            SKR_HIP(hipStreamSynchronize(st));
         }
         return SKR_OK;
     });
