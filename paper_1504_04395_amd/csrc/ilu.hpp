@@ -9,9 +9,11 @@
 // strictly triangular parts plus the diagonal, with their rows grouped into
 // dependency levels: the rows of one level depend only on earlier levels.
 //
-// Apply (device): one launch per level; thread (row, column) of the n x s
-// block computes y_i = (z_i - sum_j t_ij y_j) [/ t_ii].  A level's rows read
-// only rows of earlier levels, so in-place solves (Y == Z) are race-free.
+// Apply (device): thread (row, column) of the n x s block computes
+// y_i = (z_i - sum_j t_ij y_j) [/ t_ii], level after level: one launch per
+// level, or one workgroup that sweeps all levels when they hold little work.
+// A level's rows read only rows of earlier levels, so in-place solves
+// (Y == Z) are race-free.
 #pragma once
 
 #include <algorithm>
@@ -53,6 +55,27 @@ __global__ __launch_bounds__(kBlock) void k_trsv_level(const Ctl* ctl, TriOp<T> 
     Y[(size_t)i * s + c] = F.dg ? tdiv(acc, F.dg[i]) : acc;
 }
 
+// All levels in one workgroup (levels with little work): the workgroup sweeps
+// the levels in order with a barrier between them, which makes each level's
+// rows visible to the next.  lvl: nlev + 1 level offsets on the device.
+constexpr int kTrsvWg = 1024;
+template <class T>
+__global__ __launch_bounds__(kTrsvWg) void k_trsv_wg(const Ctl* ctl, TriOp<T> F, const int* __restrict__ lvl,
+                                                     int nlev, int s, const T* Z, T* Y) {
+    if (stopped(ctl)) return;
+    for (int l = 0; l < nlev; ++l) {
+        const int l0 = lvl[l], work = (lvl[l + 1] - l0) * s;
+        for (int g = threadIdx.x; g < work; g += kTrsvWg) {
+            const int q = g / s, c = g - q * s;
+            const int i = F.rows[l0 + q];
+            T acc = Z[(size_t)i * s + c];
+            for (int k = F.rp[i]; k < F.rp[i + 1]; ++k) acc = fma_(-F.va[k], Y[(size_t)F.ci[k] * s + c], acc);
+            Y[(size_t)i * s + c] = F.dg ? tdiv(acc, F.dg[i]) : acc;
+        }
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------------------------ host side
 inline bool hzero(double v) { return v == 0.0; }
 inline bool hzero(c64 v) { return v.x == 0.0 && v.y == 0.0; }
@@ -71,9 +94,9 @@ struct TriHost {
 };
 
 struct TriDev {
-    int *rp = nullptr, *ci = nullptr, *rows = nullptr;
+    int *rp = nullptr, *ci = nullptr, *rows = nullptr, *dlvl = nullptr;
     void *va = nullptr, *dg = nullptr;
-    std::vector<int> lvl;   // level offsets into rows (host copy, drives the launches)
+    std::vector<int> lvl;   // level offsets into rows (host copy, drives the launches; dlvl on the device)
     size_t bytes = 0;
 };
 
@@ -170,9 +193,18 @@ void ilu0_factor(int n, const std::vector<int>& rp, const std::vector<int>& ci, 
 }
 
 // Y = T^-1 Z for one triangular operator, level by level (Y may equal Z).
+// When the levels hold on average at most two passes of one workgroup
+// (rows x s <= 2048), a single workgroup sweeps them all; otherwise each
+// level is its own launch over as many workgroups as it needs.
 template <class T>
 void tri_solve(hipStream_t st, const TriDev& t, int s, const T* Z, T* Y, const Ctl* ctl) {
     const TriOp<T> op{t.rp, t.ci, (const T*)t.va, (const T*)t.dg, t.rows};
+    const int nlev = (int)t.lvl.size() - 1;
+    if (nlev < 1) return;
+    if ((long long)t.lvl[nlev] * s <= 2LL * kTrsvWg * nlev) {
+        k_trsv_wg<T><<<1, kTrsvWg, 0, st>>>(ctl, op, t.dlvl, nlev, s, Z, Y);
+        return;
+    }
     for (size_t l = 0; l + 1 < t.lvl.size(); ++l) {
         const int l0 = t.lvl[l], cnt = t.lvl[l + 1] - l0;
         const long long threads = (long long)cnt * s;

@@ -291,7 +291,7 @@ void upload_sell(DevSell& d, const HostSell& h, int C, int sigma, int n) {
 }
 
 void free_tri(TriDev& t) {
-    void* ps[] = {t.rp, t.ci, t.rows, t.va, t.dg};
+    void* ps[] = {t.rp, t.ci, t.rows, t.dlvl, t.va, t.dg};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     t = TriDev{};
@@ -319,6 +319,7 @@ void upload_tri(const TriHost<T>& h, int n, TriDev& d, hipStream_t st) {
     up((void**)&d.rows, h.rows.data(), sizeof(int) * n);
     up(&d.va, h.va.data(), sizeof(T) * h.va.size());
     if (!h.dg.empty()) up(&d.dg, h.dg.data(), sizeof(T) * n);
+    up((void**)&d.dlvl, h.lvl.data(), sizeof(int) * h.lvl.size());
     d.lvl = h.lvl;
 }
 
