@@ -5,7 +5,10 @@ Workload: 3D convection-diffusion -Lap u + beta . grad u, 7-point stencil on a
 s = 16 Gaussian right-hand sides, FP64 CSR, relative residual 1e-8.  One step
 solves the 16 right-hand sides once with each of Bl-BiCG-rQ, eGl-QMR and
 Bl-BiCGStab-rQ (48 solved right-hand sides per step).  A, B and X are resident
-in device memory before the timed region.
+in device memory before the timed region.  The three solves are independent and
+by default run at the same time, each on its own context, stream and host
+thread (--concurrent 0 runs them one after another); per_method then gives each
+solve's own wall time, which overlaps the others'.
 
 Also reported: the roofline position of the sparse x block product (the kernel
 every iteration runs; algorithmic bytes A_b + 2 n s 8 per launch, timed with HIP
@@ -129,7 +132,7 @@ ALL_METHODS = ("li_bicg", "li_qmr", "li_bicgstab", "gl_bicg", "egl_bicg", "gl_qm
                "bl_bicg", "bl_bicg_rq", "bl_bicgstab", "bl_bicgstab_rq")
 
 
-def paper_table2(pkg, ctx, inputs, reps=3):
+def paper_table2(pkg, ctx, inputs, reps=3, examples=(1, 2, 3), preconds=(None, "ilu0"), methods=None):
     """Examples 1-3 of Section 5.1 at full size, every method, without and with
     right no-fill ILU preconditioning, stopping at a 1e-10 reduction of the
     block residual or 500 iterations (Section 5.2).  Reports iterations, final
@@ -139,12 +142,12 @@ def paper_table2(pkg, ctx, inputs, reps=3):
     import numpy as np
     import torch
     rows = []
-    for k in (1, 2, 3):
+    for k in examples:
         prob = inputs.paper_example(k, "full")
         A = pkg.Matrix.from_csr(ctx, prob.A)
         B = torch.from_numpy(prob.B).cuda()
         X = torch.zeros_like(B)
-        for pc in (None, "ilu0"):
+        for pc in preconds:
             setup = None
             if pc:
                 t = time.perf_counter()
@@ -152,7 +155,7 @@ def paper_table2(pkg, ctx, inputs, reps=3):
                 setup = time.perf_counter() - t
                 log(f"ex{k} ILU(0) set-up {setup * 1e3:.1f} ms")
             table = PAPER_TABLE2_ILU if pc else PAPER_TABLE2
-            for m in ALL_METHODS:
+            for m in methods or ALL_METHODS:
                 best = None
                 for _ in range(reps):
                     torch.cuda.synchronize()
@@ -194,9 +197,17 @@ def main():
     ap.add_argument("--spmm-only", action="store_true",
                     help="only the sparse x block kernel and a plain device copy of one block "
                          "(the workload of the hardware-counter runs)")
+    ap.add_argument("--concurrent", type=int, default=1,
+                    help="1 (default): the step's three solves run at the same time, each on its own "
+                         "context, stream and host thread (same kernels and arithmetic, bit-identical "
+                         "results; their latency-bound phases overlap); 0: one after another")
     ap.add_argument("--paper-table2", action="store_true",
                     help="instead of the benchmark: Examples 1-3 of Section 5.1 at full size with "
                          "every method (tol 1e-10, 500 iterations), beside the paper's Table 2")
+    ap.add_argument("--examples", default="1,2,3", help="with --paper-table2: which examples")
+    ap.add_argument("--precond", default="none,ilu0", help="with --paper-table2: none, ilu0 or both")
+    ap.add_argument("--methods", default="", help="with --paper-table2: comma-separated subset")
+    ap.add_argument("--reps", type=int, default=3, help="with --paper-table2: solves per entry (best is kept)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is "
@@ -211,7 +222,10 @@ def main():
 
     if args.paper_table2:
         ctx = pkg.Context(0)
-        rows = paper_table2(pkg, ctx, inputs)
+        rows = paper_table2(pkg, ctx, inputs, reps=args.reps,
+                            examples=tuple(int(k) for k in args.examples.split(",")),
+                            preconds=tuple(None if p == "none" else p for p in args.precond.split(",")),
+                            methods=tuple(m for m in args.methods.split(",") if m) or None)
         print(json.dumps({"paper_examples": rows}), flush=True)
         ctx.close()
         return
@@ -238,15 +252,47 @@ def main():
     torch.cuda.synchronize()
 
     infos = {}
+    lanes = {}
+    if args.concurrent:
+        # one context (own stream, own arena) and one matrix handle per method
+        import threading
+        for m in METHODS:
+            st_m = torch.cuda.Stream()
+            c_m = pkg.Context(0, stream=st_m.cuda_stream)
+            lanes[m] = (c_m, pkg.Matrix.from_csr(c_m, A_csr), st_m)
+
+    def solve_one(m, per_method):
+        c_m, A_m = (lanes[m][0], lanes[m][1]) if lanes else (ctx, A)
+        tm = time.perf_counter()
+        X, info = pkg.solve(c_m, A_m, B, m, X=Xs[m], x0_zero=True, tol=args.tol, maxit=args.maxit)
+        if per_method is not None:
+            if lanes:
+                lanes[m][2].synchronize()
+            else:
+                torch.cuda.synchronize()
+            per_method[m] += time.perf_counter() - tm
+        infos[m] = (X, info)
 
     def solve_all(per_method=None):
-        for m in METHODS:
-            tm = time.perf_counter()
-            X, info = pkg.solve(ctx, A, B, m, X=Xs[m], x0_zero=True, tol=args.tol, maxit=args.maxit)
-            if per_method is not None:
-                torch.cuda.synchronize()
-                per_method[m] += time.perf_counter() - tm
-            infos[m] = (X, info)
+        if not lanes:
+            for m in METHODS:
+                solve_one(m, per_method)
+            return
+        errors = {}
+
+        def run(m):
+            try:
+                solve_one(m, per_method)
+            except Exception as ex:   # re-raised below, after every thread has ended
+                errors[m] = ex
+
+        ths = [threading.Thread(target=run, args=(m,)) for m in METHODS]
+        for t in ths:
+            t.start()
+        for t in ths:
+            t.join()
+        if errors:
+            raise RuntimeError(f"concurrent solves failed: {errors}")
 
     for _ in range(args.warmup):
         solve_all()
@@ -297,7 +343,7 @@ def main():
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"convdiff3d-{args.grid}^3-s16", "n": n, "nnz": nnz, "s": s,
                    "methods": list(METHODS), "tol": args.tol, "maxit": args.maxit, "format": "csr",
-                   "precision": "fp64",
+                   "precision": "fp64", "concurrent_solves": bool(args.concurrent),
                    "rhs_per_step": len(METHODS) * s, "rhs_solved_per_step": solved},
         "per_method": {m: {"iterations": infos[m][1].iterations, "status": infos[m][1].status_name,
                            "rel_res_true": infos[m][1].rel_res_true,
@@ -313,6 +359,9 @@ def main():
         prob = inputs.Problem("convdiff3d", A_csr, B_np, METHODS, {})
         out["cpu_baseline"] = cpu_baseline(prob, gpu_iters, solved, args.cpu_iters)
     print(json.dumps(out), flush=True)
+    for c_m, A_m, _ in lanes.values():
+        A_m.close()
+        c_m.close()
     A.close()
     ctx.close()
 
