@@ -181,3 +181,31 @@ def test_ilu_rejects_missing_diagonal(pkg, ctx):
     with pytest.raises(pkg.SkrError):
         A.ilu0()
     A.close()
+
+
+def test_ilu_with_sell_storage_warm_start_and_no_preprocessing(pkg, ctx):
+    """ILU(0) with SELL-C-sigma storage of A (the factors come from the CSR
+    values either way), with a nonzero initial guess, and without the QR
+    preprocessing of R0: each against the oracle's preconditioned solve."""
+    A_, B = _problem("cfg4")
+    method = "bl_bicgstab_rq"
+    ref = O.solve(A_, B, method, tol=1e-10, maxit=200, precond="ilu0")
+    for fmt in ("csr", "sell"):
+        A = pkg.Matrix.from_csr(ctx, A_, fmt=fmt).ilu0()
+        X, info = pkg.solve(ctx, A, B, method, tol=1e-10, maxit=200, precond="ilu0")
+        A.close()
+        say(f"{fmt}: it={info.iterations} (oracle {ref.iterations}) err={_rel(X, ref.X):.1e}")
+        assert info.status == 0 and abs(info.iterations - ref.iterations) <= 1
+        assert _rel(X, ref.X) < 1e-8
+    X0 = 0.5 * I.gaussian_block(A_.n, B.shape[1], seed=21, complex_=True)
+    for pre in (True, False):
+        ref = O.solve(A_, B, "egl_bicg", tol=1e-10, maxit=200, precond="ilu0", X0=X0, preprocess=pre)
+        A = pkg.Matrix.from_csr(ctx, A_).ilu0()
+        X, info = pkg.solve(ctx, A, B, "egl_bicg", X=X0.copy(), tol=1e-10, maxit=200, precond="ilu0",
+                            preprocess_qr=pre)
+        A.close()
+        say(f"warm start, preprocess={pre}: it={info.iterations} (oracle {ref.iterations}) "
+            f"err={_rel(X, ref.X):.1e}")
+        assert info.status == 0 and abs(info.iterations - ref.iterations) <= 1
+        assert _rel(X, ref.X) < 1e-8
+        np.testing.assert_allclose(info.history[:5], ref.history[:5], rtol=1e-9, atol=0)
