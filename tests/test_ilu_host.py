@@ -1,0 +1,123 @@
+"""CPU test of the library's ILU(0) set-up (host code in csrc/ilu.hpp): the
+factors against the oracle's ILU(0), the conjugate transposes, and the level
+schedules that the device triangular solves follow.  A small host-only harness
+(tests/host/ilu_host_main.cpp) is built with hipcc; no GPU is involved."""
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import inputs as I
+from oracle.ilu import ilu0
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(os.path.dirname(HERE), "paper_1504_04395_amd", "csrc")
+
+
+@pytest.fixture(scope="module")
+def harness(tmp_path_factory):
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    out = str(tmp_path_factory.mktemp("ilu") / "ilu_host")
+    subprocess.run([hipcc, "--cuda-host-only", "-O2", "-std=c++17", f"-I{CSRC}", "-x", "hip",
+                    os.path.join(HERE, "host", "ilu_host_main.cpp"), "-o", out],
+                   check=True, capture_output=True, timeout=600)
+    return out
+
+
+def _run(harness, tmp_path, A):
+    A = sp.csr_array(A)
+    A.sort_indices()
+    cplx = np.iscomplexobj(A.data)
+    f = tmp_path / "m.txt"
+    with open(f, "w") as fh:
+        fh.write(f"{A.shape[0]} {A.nnz} {int(cplx)}\n")
+        fh.write(" ".join(map(str, A.indptr)) + "\n")
+        fh.write(" ".join(map(str, A.indices)) + "\n")
+        if cplx:
+            fh.write(" ".join(f"{float(v.real)!r} {float(v.imag)!r}" for v in A.data) + "\n")
+        else:
+            fh.write(" ".join(repr(float(v)) for v in A.data) + "\n")
+    txt = subprocess.run([harness, str(f)], check=True, capture_output=True, text=True, timeout=300).stdout
+    if txt.startswith("ERROR"):
+        return txt.strip()
+    lines = txt.splitlines()
+    ops = {}
+    n = A.shape[0]
+    for b in range(4):
+        head = lines[7 * b].split()
+        name = head[0]
+        rp = np.array(lines[7 * b + 1].split(), dtype=np.int64)
+        ci = np.array(lines[7 * b + 2].split(), dtype=np.int64)
+        vals = np.array(lines[7 * b + 3].split(), dtype=np.float64)
+        dg = lines[7 * b + 4].split()
+        if cplx:
+            vals = vals[0::2] + 1j * vals[1::2]
+        if dg == ["-"]:
+            dgv = None
+        else:
+            dgv = np.array(dg, dtype=np.float64)
+            if cplx:
+                dgv = dgv[0::2] + 1j * dgv[1::2]
+        rows = np.array(lines[7 * b + 5].split(), dtype=np.int64)
+        lvl = np.array(lines[7 * b + 6].split(), dtype=np.int64)
+        T = sp.csr_array((vals, ci, rp), shape=(n, n))
+        ops[name] = (T, dgv, rows, lvl)
+    return ops
+
+
+def _check_levels(T, rows, lvl, forward):
+    n = T.shape[0]
+    assert lvl[0] == 0 and lvl[-1] == n and np.all(np.diff(lvl) > 0)
+    assert np.array_equal(np.sort(rows), np.arange(n))
+    level = np.empty(n, dtype=np.int64)
+    for l in range(len(lvl) - 1):
+        level[rows[lvl[l]:lvl[l + 1]]] = l
+    for i in range(n):
+        deps = T.indices[T.indptr[i]:T.indptr[i + 1]]
+        assert np.all(deps < i) if forward else np.all(deps > i)
+        want = (level[deps].max() + 1) if len(deps) else 0
+        assert level[i] == want
+
+
+CASES = {
+    "convdiff2d": lambda: I.convdiff2d(12, (20.0, 20.0)).to_scipy(),
+    "powerlaw_complex": lambda: I.powerlaw(300, seed=7, lo=4, hi=20, mean=8.0).to_scipy(),
+    "paper_ex2_small": lambda: I.paper_example(2, "small").A.to_scipy(),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_host_ilu_matches_oracle_and_levels_are_valid(harness, tmp_path, case):
+    A = sp.csr_array(CASES[case]())
+    ops = _run(harness, tmp_path, A)
+    Lo, Uo = ilu0(A)
+    L, _, rL, lL = ops["L"]
+    U, dU, rU, lU = ops["U"]
+    UH, dUH, rUH, lUH = ops["UH"]
+    LH, _, rLH, lLH = ops["LH"]
+    n = A.shape[0]
+    Lfull = (L + sp.eye_array(n)).toarray()
+    Ufull = (U + sp.diags_array(dU)).toarray()
+    scale = np.abs(A.toarray()).max()
+    assert np.abs(Lfull - Lo.toarray()).max() < 1e-13
+    assert np.abs(Ufull - Uo.toarray()).max() < 1e-13 * scale
+    assert np.array_equal(UH.toarray(), U.conj().T.toarray())
+    assert np.array_equal(LH.toarray(), L.conj().T.toarray())
+    assert np.array_equal(dUH, np.conj(dU))
+    _check_levels(L, rL, lL, True)
+    _check_levels(U, rU, lU, False)
+    _check_levels(UH, rUH, lUH, True)
+    _check_levels(LH, rLH, lLH, False)
+
+
+def test_host_ilu_reports_missing_diagonal_and_zero_pivot(harness, tmp_path):
+    A = sp.csr_array(np.array([[0.0, 1.0, 0.0], [1.0, 1.0, 0.0], [0.0, 1.0, 2.0]]))
+    A.eliminate_zeros()
+    assert _run(harness, tmp_path, A).startswith("ERROR")
+    B = sp.csr_array(np.array([[1.0, 1.0], [1.0, 1.0]]))     # u_22 = 1 - 1 = 0
+    assert "pivot" in _run(harness, tmp_path, B)
