@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "blk.hpp"
+#include "cblk.hpp"
 #include "common.hpp"
 #include "glk.hpp"
 #include "ilu.hpp"
@@ -260,6 +261,17 @@ void tri_pass(Env<T>& e, int slot, int cond, int nchain, int add_shift, int mode
         else
             k_bl_tri16<T, 3, true><<<e.nb, kBlock, 0, e.st>>>(e.ctl, slot, cond, nchain, add_shift, e.tl, mode,
                                                              e.mats, Z, Out, Other, e.part);
+    } else if constexpr (Tr<T>::cplx) {
+        const bool oth = (mode & (TRI_G_OTHER_OUT | TRI_G_OUT_OTHER)) != 0;
+        if (nchain + add_shift <= 1 && !oth)
+            k_bl_tric<T, J, 1, false><<<e.nb, kBlock, 0, e.st>>>(e.ctl, slot, cond, nchain, add_shift, e.tl, mode,
+                                                                 e.mats, Z, Out, Other, e.part);
+        else if (!oth)
+            k_bl_tric<T, J, 3, false><<<e.nb, kBlock, 0, e.st>>>(e.ctl, slot, cond, nchain, add_shift, e.tl, mode,
+                                                                 e.mats, Z, Out, Other, e.part);
+        else
+            k_bl_tric<T, J, 3, true><<<e.nb, kBlock, 0, e.st>>>(e.ctl, slot, cond, nchain, add_shift, e.tl, mode,
+                                                                e.mats, Z, Out, Other, e.part);
     } else {
         k_bl_tri<T, J><<<e.nb, kBlock, mat_lds(e.s, 3, 1), e.st>>>(e.ctl, slot, cond, nchain, add_shift, e.tl, mode,
                                                                     e.mats, Z, Out, Other, e.part);
@@ -298,6 +310,9 @@ void axpm(Env<T>& e, int mslot, int gslot, const T* A, const T* B, const T* C, T
     if constexpr (!Tr<T>::cplx && J == 1) {
         k_bl_axpm16<T, GRAM><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.tl, e.mats, mslot, e.sc, gslot, A, B, C, Out,
                                                         e.part);
+    } else if constexpr (Tr<T>::cplx) {
+        k_bl_axpmc<T, J, GRAM><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.tl, e.mats, mslot, e.sc, gslot, A, B, C, Out,
+                                                          e.part);
     } else {
         k_bl_axpm<T, J, GRAM><<<e.nb, kBlock, mat_lds(e.s, 1, 1), e.st>>>(e.ctl, e.tl, e.mats, mslot, e.sc, gslot,
                                                                            A, B, C, Out, e.part);
@@ -308,6 +323,8 @@ template <class T, int J>
 void blrq_updz(Env<T>& e, T* X, const T* V, const T* Q, const T* W, T* Z) {
     if constexpr (!Tr<T>::cplx && J == 1) {
         k_blrq_updz16<T><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.tl, e.mats, X, V, Q, W, Z, e.part);
+    } else if constexpr (Tr<T>::cplx) {
+        k_blrq_updzc<T, J><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.tl, e.mats, X, V, Q, W, Z, e.part);
     } else {
         k_blrq_updz<T, J><<<e.nb, kBlock, mat_lds(e.s, 2, 2), e.st>>>(e.ctl, e.tl, e.mats, X, V, Q, W, Z, e.part);
     }
@@ -317,6 +334,8 @@ template <class T, int J>
 void blst_upd(Env<T>& e, T* X, const T* U, const T* St, const T* Tt, T* Z) {
     if constexpr (!Tr<T>::cplx && J == 1) {
         k_blst_upd16<T><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.tl, e.mats, e.sc, X, U, St, Tt, Z, e.part);
+    } else if constexpr (Tr<T>::cplx) {
+        k_blst_updc<T, J><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.tl, e.mats, e.sc, X, U, St, Tt, Z, e.part);
     } else {
         k_blst_upd<T, J><<<e.nb, kBlock, mat_lds(e.s, 2, 2), e.st>>>(e.ctl, e.tl, e.mats, e.sc, X, U, St, Tt, Z,
                                                                     e.part);
