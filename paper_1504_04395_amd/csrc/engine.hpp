@@ -158,10 +158,29 @@ void spmm_j(Env<T>& e, const Operand<T>& op, const Layout& ly, const T* X, T* Y,
         e.pc_on = true;
         return;
     }
+    // s > 16 Gram epilogues as separate streaming passes over Y and Z: fused,
+    // the s x s accumulators would cut the gather loop's occupancy to 1-2 waves
+    // per SIMD
+    auto gram_after = [&](auto& ep) {
+        const int ss = ly.s * ly.s;
+        if constexpr (std::is_same<std::decay_t<decltype(ep)>, EpiGram<T, 2>>::value) {
+            k_bl_gram<T, 2><<<e.nb, kBlock, 0, e.st>>>(ctl, e.tl, ep.Z, Y, ep.part);   // Z^H Y
+        } else {
+            k_bl_gram<T, 2><<<e.nb, kBlock, 0, e.st>>>(ctl, e.tl, Y, ep.Z, ep.part, 2 * ss, 0);   // Y^H Z
+            SKR_LAUNCHED();
+            k_bl_gram<T, 2><<<e.nb, kBlock, 0, e.st>>>(ctl, e.tl, Y, Y, ep.part, 2 * ss, ss);      // Y^H Y
+        }
+    };
     if (op.sell) {
         int nchunks = (e.n + op.sl.C - 1) / op.sl.C;
         int cpb = (nchunks + e.nb - 1) / e.nb;
-        k_spmm_sell<T, J, Epi><<<e.nb, kBlock, 0, e.st>>>(ctl, op.sl, ly, cpb, X, Y, epi);
+        if constexpr (J16 == 2 && EpiIsGram<Epi>::value && J == 2) {
+            k_spmm_sell<T, J, EpiNone><<<e.nb, kBlock, 0, e.st>>>(ctl, op.sl, ly, cpb, X, Y, EpiNone{});
+            SKR_LAUNCHED();
+            gram_after(epi);
+        } else {
+            k_spmm_sell<T, J, Epi><<<e.nb, kBlock, 0, e.st>>>(ctl, op.sl, ly, cpb, X, Y, epi);
+        }
     } else if (!Tr<T>::cplx && J16 == 1 && ly.s % 2 == 0) {
         if constexpr (!Tr<T>::cplx && J16 == 1) {
             // real, even s <= 16: 8 lanes per row, two columns per lane
@@ -174,19 +193,9 @@ void spmm_j(Env<T>& e, const Operand<T>& op, const Layout& ly, const T* X, T* Y,
         const int step = 32;                           // RP * 16 rows per workgroup pass (upper bound)
         const int per_xcd = ((e.n + 7) / 8 + step - 1) / step * step;
         if constexpr (J16 == 2 && EpiIsGram<Epi>::value && J == 2) {
-            // s > 16: the fused s x s Gram accumulators would cut the gather
-            // loop's occupancy to 1-2 waves per SIMD, so the product runs
-            // alone and the Gram is a separate streaming pass over Y and Z
             k_spmm_csr<T, 2, EpiNone><<<e.nb, kBlock, 0, e.st>>>(ctl, op.csr, l16, per_xcd, X, Y, EpiNone{});
             SKR_LAUNCHED();
-            const int ss = ly.s * ly.s;
-            if constexpr (std::is_same<Epi, EpiGram<T, 2>>::value) {
-                k_bl_gram<T, 2><<<e.nb, kBlock, 0, e.st>>>(ctl, e.tl, epi.Z, Y, epi.part);   // Z^H Y
-            } else {
-                k_bl_gram<T, 2><<<e.nb, kBlock, 0, e.st>>>(ctl, e.tl, Y, epi.Z, epi.part, 2 * ss, 0);   // Y^H Z
-                SKR_LAUNCHED();
-                k_bl_gram<T, 2><<<e.nb, kBlock, 0, e.st>>>(ctl, e.tl, Y, Y, epi.part, 2 * ss, ss);      // Y^H Y
-            }
+            gram_after(epi);
         } else {
             k_spmm_csr<T, J16, Epi><<<e.nb, kBlock, 0, e.st>>>(ctl, op.csr, l16, per_xcd, X, Y, epi);
         }
