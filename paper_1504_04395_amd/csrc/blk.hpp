@@ -244,89 +244,6 @@ __device__ inline void gram_final(const c64* __restrict__ part2, int p2, int E, 
 // ---------------------------------------------------------------- triangular pass
 enum { TRI_WRITE = 1, TRI_G_OUT_OUT = 2, TRI_G_OTHER_OUT = 4, TRI_G_OUT_OTHER = 8 };
 
-// out = Z S1^{-1} S2^{-1} [S3^{-1}]: the first `nchain` inverse factors of QR
-// slot `slot`, applied one after the other, plus S3^{-1} when `add_shift` and
-// the slot used the shifted first pass.  cond: run only when the shifted pass
-// was used.  Out may alias Z (each row is read before it is written, by the
-// same lanes).
-template <class T, int J>
-__global__ __launch_bounds__(kBlock) void k_bl_tri(const Ctl* ctl, int slot, int cond, int nchain, int add_shift,
-                                                   Tile16 tl, int mode, const c64* __restrict__ mats, const T* Z,
-                                                   T* Out, const T* __restrict__ Other, c64* part) {
-    if (stopped(ctl)) return;
-    const int shifted = ctl->qr_shift[slot];
-    if (cond && !shifted) return;
-    constexpr int RP = RowPasses<T, J>::value;
-    const int nc = nchain + (add_shift && shifted ? 1 : 0);
-    extern __shared__ c64 dyn[];
-    using VV = Val<T>;
-    const int s = tl.s, ss = s * s;
-    const int base = slot == 0 ? M_S1 : M_T1;
-    VV* M = reinterpret_cast<VV*>(dyn);   // up to 3 matrices
-    lds_load_mat(M, mats + (size_t)(base + 1) * ss, s);
-    if (nc > 1) lds_load_mat(M + ss, mats + (size_t)(base + 3) * ss, s);
-    if (nc > 2) lds_load_mat(M + 2 * ss, mats + (size_t)(base + 5) * ss, s);
-    __syncthreads();
-    const int ln = threadIdx.x & 15;
-    Coef<T, J> cf0, cf1, cf2;
-    cf0.load(M, s, ln);
-    if (nc > 1) cf1.load(M + ss, s, ln);
-    if (nc > 2) cf2.load(M + 2 * ss, s, ln);
-    GramAcc<J, Tr<T>::cplx> g;
-    g.clear();
-    SKR_TILE_LOOP_RP(tl, RP) {
-        VV o[RP][J];
-#pragma unroll
-        for (int p = 0; p < RP; ++p) {
-            const int i = base_ + 16 * p + grp;
-            load_row<T, J>(Z, i, i < r1_, lane, s, o[p]);
-        }
-#pragma unroll
-        for (int p = 0; p < RP; ++p) {
-            VV t[J];
-#pragma unroll
-            for (int j = 0; j < J; ++j) t[j] = vzero<VV>();
-            cf0.apply(o[p], lane, t);
-            if (nc > 1) {
-#pragma unroll
-                for (int j = 0; j < J; ++j) o[p][j] = vzero<VV>();
-                cf1.apply(t, lane, o[p]);
-                if (nc > 2) {
-#pragma unroll
-                    for (int j = 0; j < J; ++j) t[j] = vzero<VV>();
-                    cf2.apply(o[p], lane, t);
-#pragma unroll
-                    for (int j = 0; j < J; ++j) o[p][j] = t[j];
-                }
-            } else {
-#pragma unroll
-                for (int j = 0; j < J; ++j) o[p][j] = t[j];
-            }
-        }
-#pragma unroll
-        for (int p = 0; p < RP; ++p) {
-            const int i = base_ + 16 * p + grp;
-            const bool valid = i < r1_;
-            if (!valid) {
-#pragma unroll
-                for (int j = 0; j < J; ++j) o[p][j] = vzero<VV>();
-            }
-            if (mode & TRI_WRITE) store_row<T, J>(Out, i, valid, lane, s, o[p]);
-            if (mode & TRI_G_OUT_OUT) g.add(o[p], o[p]);
-            if (mode & (TRI_G_OTHER_OUT | TRI_G_OUT_OTHER)) {
-                VV ot[J];
-                load_row<T, J>(Other, i, valid, lane, s, ot);
-                if (mode & TRI_G_OTHER_OUT) g.add(ot, o[p]);
-                else g.add(o[p], ot);
-            }
-        }
-    }
-    if (mode & (TRI_G_OUT_OUT | TRI_G_OTHER_OUT | TRI_G_OUT_OTHER)) {
-        __syncthreads();
-        g.store(s, dyn, part + (size_t)blockIdx.x * s * s);
-    }
-}
-
 // ------------------------------------------------ real s <= 16: MFMA row tiles
 // A wave owns 16 consecutive rows.  Lane L = c + 16 q holds, in register v, the
 // element (row 4v + q, column c) of the tile: four coalesced 16-column loads,
@@ -377,7 +294,12 @@ __device__ inline void tile_store(T* P, int b, int r1, int s, int c, int q, cons
     }
 }
 
-// k_bl_tri for real blocks with s <= 16 (same arguments and results).  NC: the
+// CholeskyQR triangular pass, real blocks with s <= 16: out = Z S1^{-1} S2^{-1}
+// [S3^{-1}], the first `nchain` inverse factors of QR slot `slot` applied one
+// after the other, plus S3^{-1} when `add_shift` and the slot used the shifted
+// first pass; cond: run only when the shifted pass was used; mode: write out
+// (TRI_WRITE) and/or accumulate a Gram of out (TRI_G_*).  Out may alias Z (each
+// tile is read before it is written, by the same lanes).  NC: the
 // most inverse factors this instance applies (1 or 3); OTH: whether the Gram's
 // second operand is another block (fewer live registers when it is not).
 template <class T, int NC, bool OTH>
@@ -457,7 +379,8 @@ __global__ __launch_bounds__(kBlock) void k_bl_tri16(const Ctl* ctl, int slot, i
     }
 }
 
-// k_bl_axpm for real blocks with s <= 16 (same arguments and results).
+// Out = A + (B + gamma C) M [+ part = Out^H Out] for real blocks with s <= 16;
+// A or C may be null; Out may alias A or B.
 template <class T, bool GRAM>
 __global__ __launch_bounds__(kBlock) void k_bl_axpm16(const Ctl* ctl, Tile16 tl, const c64* __restrict__ mats,
                                                       int mslot, const c64* __restrict__ sc, int gslot, const T* A,
@@ -511,7 +434,8 @@ __global__ __launch_bounds__(kBlock) void k_bl_axpm16(const Ctl* ctl, Tile16 tl,
     }
 }
 
-// k_blrq_updz for real blocks with s <= 16.
+// Bl-BiCG-rQ, real blocks with s <= 16: X += V (alpha C); Z = Q - W alpha;
+// part = Z^H Z.  mats holds -alpha.
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_blrq_updz16(const Ctl* ctl, Tile16 tl, const c64* __restrict__ mats,
                                                         T* __restrict__ X, const T* __restrict__ Vb,
@@ -556,7 +480,8 @@ __global__ __launch_bounds__(kBlock) void k_blrq_updz16(const Ctl* ctl, Tile16 t
     g.store(s, glds, part + (size_t)blockIdx.x * s * s);
 }
 
-// k_blst_upd for real blocks with s <= 16.
+// Bl-BiCGStab-rQ, real blocks with s <= 16: X += U (a C) + S~ (omega C);
+// Z = S~ - omega T~; part = Z^H Z.
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_blst_upd16(const Ctl* ctl, Tile16 tl, const c64* __restrict__ mats,
                                                        const c64* __restrict__ sc, T* __restrict__ X,
@@ -601,162 +526,6 @@ __global__ __launch_bounds__(kBlock) void k_blst_upd16(const Ctl* ctl, Tile16 tl
     }
     __syncthreads();
     g.store(s, glds, part + (size_t)blockIdx.x * s * s);
-}
-
-// Out = A + (B + gamma C) M  [+ part = Out^H Out]; A or C may be null; Out may alias A or B.
-template <class T, int J, bool GRAM>
-__global__ __launch_bounds__(kBlock) void k_bl_axpm(const Ctl* ctl, Tile16 tl, const c64* __restrict__ mats, int mslot,
-                                                    const c64* __restrict__ sc, int gslot, const T* A,
-                                                    const T* B, const T* __restrict__ Cm, T* Out, c64* part) {
-    if (stopped(ctl)) return;
-    constexpr int RP = RowPasses<T, J>::value;
-    extern __shared__ c64 dyn[];
-    using VV = Val<T>;
-    const int s = tl.s;
-    VV* M = reinterpret_cast<VV*>(dyn);
-    lds_load_mat(M, mats + (size_t)mslot * s * s, s);
-    __syncthreads();
-    Coef<T, J> cf;
-    cf.load(M, s, threadIdx.x & 15);
-    const VV gamma = Cm ? vfrom(sc[gslot], VV{}) : vzero<VV>();
-    GramAcc<J, Tr<T>::cplx> g;
-    g.clear();
-    SKR_TILE_LOOP_RP(tl, RP) {
-        VV b[RP][J], o[RP][J];
-#pragma unroll
-        for (int p = 0; p < RP; ++p) {
-            const int i = base_ + 16 * p + grp;
-            const bool valid = i < r1_;
-            load_row<T, J>(B, i, valid, lane, s, b[p]);
-            if (Cm) {
-                VV cc[J];
-                load_row<T, J>(Cm, i, valid, lane, s, cc);
-#pragma unroll
-                for (int j = 0; j < J; ++j) b[p][j] = vfma(gamma, cc[j], b[p][j]);
-            }
-            if (A) load_row<T, J>(A, i, valid, lane, s, o[p]);
-            else {
-#pragma unroll
-                for (int j = 0; j < J; ++j) o[p][j] = vzero<VV>();
-            }
-        }
-#pragma unroll
-        for (int p = 0; p < RP; ++p) {
-            const int i = base_ + 16 * p + grp;
-            const bool valid = i < r1_;
-            cf.apply(b[p], lane, o[p]);
-            store_row<T, J>(Out, i, valid, lane, s, o[p]);
-            if (GRAM) {
-                if (!valid) {
-#pragma unroll
-                    for (int j = 0; j < J; ++j) o[p][j] = vzero<VV>();
-                }
-                g.add(o[p], o[p]);
-            }
-        }
-    }
-    if (GRAM) {
-        __syncthreads();
-        g.store(s, dyn, part + (size_t)blockIdx.x * s * s);
-    }
-}
-
-// Bl-BiCG-rQ: X += V (alpha C); Z = Q - W alpha; part = Z^H Z.  mats holds -alpha.
-template <class T, int J>
-__global__ __launch_bounds__(kBlock) void k_blrq_updz(const Ctl* ctl, Tile16 tl, const c64* __restrict__ mats,
-                                                      T* __restrict__ X, const T* __restrict__ Vb,
-                                                      const T* __restrict__ Q, const T* __restrict__ W,
-                                                      T* __restrict__ Z, c64* part) {
-    if (stopped(ctl)) return;
-    constexpr int RP = RowPasses<T, J>::value;
-    extern __shared__ c64 dyn[];
-    using VV = Val<T>;
-    const int s = tl.s;
-    VV* Ma = reinterpret_cast<VV*>(dyn);  // -alpha
-    VV* Mac = Ma + s * s;                 // alpha C
-    lds_load_mat(Ma, mats + (size_t)M_ALPHA * s * s, s);
-    lds_load_mat(Mac, mats + (size_t)M_ALPHAC * s * s, s);
-    __syncthreads();
-    Coef<T, J> ca, cac;
-    ca.load(Ma, s, threadIdx.x & 15);
-    cac.load(Mac, s, threadIdx.x & 15);
-    GramAcc<J, Tr<T>::cplx> g;
-    g.clear();
-    SKR_TILE_LOOP_RP(tl, RP) {
-        VV v[RP][J], w[RP][J], x[RP][J], z[RP][J];
-#pragma unroll
-        for (int p = 0; p < RP; ++p) {
-            const int i = base_ + 16 * p + grp;
-            const bool valid = i < r1_;
-            load_row<T, J>(Vb, i, valid, lane, s, v[p]);
-            load_row<T, J>(W, i, valid, lane, s, w[p]);
-            load_row<T, J>(X, i, valid, lane, s, x[p]);
-            load_row<T, J>(Q, i, valid, lane, s, z[p]);
-        }
-#pragma unroll
-        for (int p = 0; p < RP; ++p) {
-            const int i = base_ + 16 * p + grp;
-            const bool valid = i < r1_;
-            cac.apply(v[p], lane, x[p]);
-            ca.apply(w[p], lane, z[p]);
-            store_row<T, J>(X, i, valid, lane, s, x[p]);
-            store_row<T, J>(Z, i, valid, lane, s, z[p]);
-            g.add(z[p], z[p]);
-        }
-    }
-    __syncthreads();
-    g.store(s, dyn, part + (size_t)blockIdx.x * s * s);
-}
-
-// Bl-BiCGStab-rQ: X += U (a C) + S~ (omega C); Z = S~ - omega T~; part = Z^H Z
-template <class T, int J>
-__global__ __launch_bounds__(kBlock) void k_blst_upd(const Ctl* ctl, Tile16 tl, const c64* __restrict__ mats,
-                                                     const c64* __restrict__ sc, T* __restrict__ X,
-                                                     const T* __restrict__ U, const T* __restrict__ St,
-                                                     const T* __restrict__ Tt, T* __restrict__ Z, c64* part) {
-    if (stopped(ctl)) return;
-    constexpr int RP = RowPasses<T, J>::value;
-    extern __shared__ c64 dyn[];
-    using VV = Val<T>;
-    const int s = tl.s;
-    VV* Mac = reinterpret_cast<VV*>(dyn);  // a C
-    VV* Mwc = Mac + s * s;                 // omega C
-    lds_load_mat(Mac, mats + (size_t)M_AC * s * s, s);
-    lds_load_mat(Mwc, mats + (size_t)M_WC * s * s, s);
-    __syncthreads();
-    Coef<T, J> cac, cwc;
-    cac.load(Mac, s, threadIdx.x & 15);
-    cwc.load(Mwc, s, threadIdx.x & 15);
-    const VV mw = vfrom(-sc[SC_OMEGA], VV{});
-    GramAcc<J, Tr<T>::cplx> g;
-    g.clear();
-    SKR_TILE_LOOP_RP(tl, RP) {
-        VV u[RP][J], st[RP][J], tt[RP][J], x[RP][J];
-#pragma unroll
-        for (int p = 0; p < RP; ++p) {
-            const int i = base_ + 16 * p + grp;
-            const bool valid = i < r1_;
-            load_row<T, J>(U, i, valid, lane, s, u[p]);
-            load_row<T, J>(St, i, valid, lane, s, st[p]);
-            load_row<T, J>(Tt, i, valid, lane, s, tt[p]);
-            load_row<T, J>(X, i, valid, lane, s, x[p]);
-        }
-#pragma unroll
-        for (int p = 0; p < RP; ++p) {
-            const int i = base_ + 16 * p + grp;
-            const bool valid = i < r1_;
-            cac.apply(u[p], lane, x[p]);
-            cwc.apply(st[p], lane, x[p]);
-            VV z[J];
-#pragma unroll
-            for (int j = 0; j < J; ++j) z[j] = vfma(mw, tt[p][j], st[p][j]);
-            store_row<T, J>(X, i, valid, lane, s, x[p]);
-            store_row<T, J>(Z, i, valid, lane, s, z);
-            g.add(z, z);
-        }
-    }
-    __syncthreads();
-    g.store(s, dyn, part + (size_t)blockIdx.x * s * s);
 }
 
 // ---------------------------------------------------------------- coefficient kernels

@@ -1,7 +1,10 @@
-// Complex block kernels on MFMA row tiles (complex storage, s <= 16 J, J = 1
-// or 2): the CholeskyQR triangular pass, the s x s-coefficient updates of the
-// block methods and the Bl-BiCG-rQ / Bl-BiCGStab-rQ fused updates, with the
-// same arguments and results as their row-layout versions in blk.hpp.
+// Block kernels on MFMA row tiles for complex storage (s <= 16 J, J = 1 or 2)
+// and for real storage with 16 < s <= 32: the CholeskyQR triangular pass, the
+// s x s-coefficient updates of the block methods and the Bl-BiCG-rQ /
+// Bl-BiCGStab-rQ fused updates, with the same arguments and results as the
+// real s <= 16 kernels in blk.hpp (k_bl_tri16, k_bl_axpm16, k_blrq_updz16,
+// k_blst_upd16).  Real data carry zero imaginary parts, which
+// the real instances neither load nor multiply (one MFMA per slab, not four).
 //
 // Tile layout: a wave owns 16 consecutive rows; lane L = c + 16 q holds, in
 // register v, the element (row 4v + q, column c + 16 h) for h < J, real and
@@ -76,8 +79,8 @@ __device__ inline void cmat_lds(double* Mr, double* Mi, const c64* __restrict__ 
 }
 
 // o += x M for the wave's tile x; M from LDS (Mr, Mi); tw: this wave's LDS tile
-// (2 * 16 * cld<J>() doubles)
-template <int J>
+// (2 * 16 * cld<J>() doubles).  C: complex arithmetic (else real parts only).
+template <int J, bool C>
 __device__ inline void capply(const CTile<J>& x, const double* Mr, const double* Mi, double* tw, int c, int q,
                               CTile<J>& o) {
     constexpr int LD = cld<J>();
@@ -88,7 +91,7 @@ __device__ inline void capply(const CTile<J>& x, const double* Mr, const double*
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             twr[(4 * v + q) * LD + 16 * h + c] = x.r[h][v];
-            twi[(4 * v + q) * LD + 16 * h + c] = x.i[h][v];
+            if (C) twi[(4 * v + q) * LD + 16 * h + c] = x.i[h][v];
         }
     __builtin_amdgcn_wave_barrier();
     d4 ar[J], ai[J];
@@ -99,14 +102,17 @@ __device__ inline void capply(const CTile<J>& x, const double* Mr, const double*
     }
 #pragma unroll
     for (int t = 0; t < 4 * J; ++t) {
-        const double xr = twr[c * LD + 4 * t + q], xi = twi[c * LD + 4 * t + q];
+        const double xr = twr[c * LD + 4 * t + q];
 #pragma unroll
         for (int jb = 0; jb < J; ++jb) {
-            const double mr = Mr[(4 * t + q) * LD + 16 * jb + c], mi = Mi[(4 * t + q) * LD + 16 * jb + c];
+            const double mr = Mr[(4 * t + q) * LD + 16 * jb + c];
             ar[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr, mr, ar[jb], 0, 0, 0);
-            ar[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-xi, mi, ar[jb], 0, 0, 0);
-            ai[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr, mi, ai[jb], 0, 0, 0);
-            ai[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(xi, mr, ai[jb], 0, 0, 0);
+            if (C) {
+                const double xi = twi[c * LD + 4 * t + q], mi = Mi[(4 * t + q) * LD + 16 * jb + c];
+                ar[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-xi, mi, ar[jb], 0, 0, 0);
+                ai[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr, mi, ai[jb], 0, 0, 0);
+                ai[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(xi, mr, ai[jb], 0, 0, 0);
+            }
         }
     }
     __builtin_amdgcn_wave_barrier();
@@ -120,8 +126,8 @@ __device__ inline void capply(const CTile<J>& x, const double* Mr, const double*
 }
 
 // Gram accumulation of y^H x over the tile's four row groups
-template <int J>
-__device__ inline void cgram_add(GramAcc<J, true>& g, const CTile<J>& y, const CTile<J>& x) {
+template <int J, bool C>
+__device__ inline void cgram_add(GramAcc<J, C>& g, const CTile<J>& y, const CTile<J>& x) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         c64 yv[J], xv[J];
@@ -142,13 +148,14 @@ __device__ inline void cgram_add(GramAcc<J, true>& g, const CTile<J>& y, const C
     const int r1_ = min((tl).n, r0_ + (tl).rpc)
 
 // ---------------------------------------------------------------- kernels
-// k_bl_tri for complex blocks.  NC: the most inverse factors this instance
+// CholeskyQR triangular pass (as k_bl_tri16).  NC: the most inverse factors this instance
 // applies (1 or 3); OTH: whether the Gram's second operand is another block.
 template <class T, int J, int NC, bool OTH>
 __global__ __launch_bounds__(kBlock) void k_bl_tric(const Ctl* ctl, int slot, int cond, int nchain, int add_shift,
                                                     Tile16 tl, int mode, const c64* __restrict__ mats, const T* Z,
                                                     T* Out, const T* __restrict__ Other, c64* part) {
     if (stopped(ctl)) return;
+    constexpr bool C = Tr<T>::cplx;
     const int shifted = ctl->qr_shift[slot];
     if (cond && !shifted) return;
     const int nc = nchain + (add_shift && shifted ? 1 : 0);
@@ -165,7 +172,7 @@ __global__ __launch_bounds__(kBlock) void k_bl_tric(const Ctl* ctl, int slot, in
     __syncthreads();
     SKR_CTILE_RANGE(tl);
     double* tw = tiles[w_];
-    GramAcc<J, true> g;
+    GramAcc<J, C> g;
     g.clear();
     CTile<J> xn, otn;
     ctile_zero(otn);
@@ -183,24 +190,24 @@ __global__ __launch_bounds__(kBlock) void k_bl_tric(const Ctl* ctl, int slot, in
         }
         CTile<J> o;
         ctile_zero(o);
-        capply<J>(x, Ms[0][0], Ms[0][1], tw, c, q, o);
+        capply<J, C>(x, Ms[0][0], Ms[0][1], tw, c, q, o);
         if constexpr (NC > 1) {
             if (nc > 1) {
                 const CTile<J> y = o;
                 ctile_zero(o);
-                capply<J>(y, Ms[1][0], Ms[1][1], tw, c, q, o);
+                capply<J, C>(y, Ms[1][0], Ms[1][1], tw, c, q, o);
             }
             if (nc > 2) {
                 const CTile<J> y = o;
                 ctile_zero(o);
-                capply<J>(y, Ms[2][0], Ms[2][1], tw, c, q, o);
+                capply<J, C>(y, Ms[2][0], Ms[2][1], tw, c, q, o);
             }
         }
         if (mode & TRI_WRITE) ctile_store<T, J>(Out, b, r1_, s, c, q, o);
         if (mode & (TRI_G_OUT_OUT | TRI_G_OTHER_OUT | TRI_G_OUT_OTHER)) {
-            if (!OTH) cgram_add<J>(g, o, o);
-            else if (mode & TRI_G_OTHER_OUT) cgram_add<J>(g, ot, o);
-            else cgram_add<J>(g, o, ot);
+            if (!OTH) cgram_add<J, C>(g, o, o);
+            else if (mode & TRI_G_OTHER_OUT) cgram_add<J, C>(g, ot, o);
+            else cgram_add<J, C>(g, o, ot);
         }
     }
     if (mode & (TRI_G_OUT_OUT | TRI_G_OTHER_OUT | TRI_G_OUT_OTHER)) {
@@ -209,7 +216,7 @@ __global__ __launch_bounds__(kBlock) void k_bl_tric(const Ctl* ctl, int slot, in
     }
 }
 
-// k_bl_axpm for complex blocks: Out = A + (B + gamma C) M [+ part = Out^H Out];
+// Out = A + (B + gamma C) M [+ part = Out^H Out];
 // A or C may be null; Out may alias A or B (a tile is loaded before it is
 // written, by the same lanes, and later tiles are never written early).
 template <class T, int J, bool GRAM>
@@ -217,6 +224,7 @@ __global__ __launch_bounds__(kBlock) void k_bl_axpmc(const Ctl* ctl, Tile16 tl, 
                                                      int mslot, const c64* __restrict__ sc, int gslot, const T* A,
                                                      const T* B, const T* __restrict__ Cm, T* Out, c64* part) {
     if (stopped(ctl)) return;
+    constexpr bool C = Tr<T>::cplx;
     constexpr int S = 16 * J, LD = cld<J>();
     const int s = tl.s;
     __shared__ double Ms[2][S * LD];
@@ -226,7 +234,7 @@ __global__ __launch_bounds__(kBlock) void k_bl_axpmc(const Ctl* ctl, Tile16 tl, 
     const c64 gamma = Cm ? sc[gslot] : c64{0.0, 0.0};
     SKR_CTILE_RANGE(tl);
     double* tw = tiles[w_];
-    GramAcc<J, true> g;
+    GramAcc<J, C> g;
     g.clear();
     CTile<J> bn_;
     int b = r0_ + 16 * w_;
@@ -250,9 +258,9 @@ __global__ __launch_bounds__(kBlock) void k_bl_axpmc(const Ctl* ctl, Tile16 tl, 
         CTile<J> o;
         if (A) ctile_load<T, J>(A, b, r1_, s, c, q, o);
         else ctile_zero(o);
-        capply<J>(x, Ms[0], Ms[1], tw, c, q, o);
+        capply<J, C>(x, Ms[0], Ms[1], tw, c, q, o);
         ctile_store<T, J>(Out, b, r1_, s, c, q, o);
-        if (GRAM) cgram_add<J>(g, o, o);
+        if (GRAM) cgram_add<J, C>(g, o, o);
     }
     if (GRAM) {
         __syncthreads();
@@ -260,13 +268,14 @@ __global__ __launch_bounds__(kBlock) void k_bl_axpmc(const Ctl* ctl, Tile16 tl, 
     }
 }
 
-// k_blrq_updz for complex blocks: X += V (alpha C); Z = Q - W alpha; part = Z^H Z.
+// Bl-BiCG-rQ: X += V (alpha C); Z = Q - W alpha; part = Z^H Z.
 template <class T, int J>
 __global__ __launch_bounds__(kBlock) void k_blrq_updzc(const Ctl* ctl, Tile16 tl, const c64* __restrict__ mats,
                                                        T* __restrict__ X, const T* __restrict__ Vb,
                                                        const T* __restrict__ Q, const T* __restrict__ W,
                                                        T* __restrict__ Z, c64* part) {
     if (stopped(ctl)) return;
+    constexpr bool C = Tr<T>::cplx;
     constexpr int S = 16 * J, LD = cld<J>();
     const int s = tl.s;
     __shared__ double Ma[2][S * LD];    // -alpha
@@ -277,7 +286,7 @@ __global__ __launch_bounds__(kBlock) void k_blrq_updzc(const Ctl* ctl, Tile16 tl
     __syncthreads();
     SKR_CTILE_RANGE(tl);
     double* tw = tiles[w_];
-    GramAcc<J, true> g;
+    GramAcc<J, C> g;
     g.clear();
     for (int b = r0_ + 16 * w_; b < r1_; b += 16 * kWaves) {
         CTile<J> v, w, x, z;
@@ -285,17 +294,17 @@ __global__ __launch_bounds__(kBlock) void k_blrq_updzc(const Ctl* ctl, Tile16 tl
         ctile_load<T, J>(W, b, r1_, s, c, q, w);
         ctile_load<T, J>(X, b, r1_, s, c, q, x);
         ctile_load<T, J>(Q, b, r1_, s, c, q, z);
-        capply<J>(v, Mac[0], Mac[1], tw, c, q, x);
+        capply<J, C>(v, Mac[0], Mac[1], tw, c, q, x);
         ctile_store<T, J>(X, b, r1_, s, c, q, x);
-        capply<J>(w, Ma[0], Ma[1], tw, c, q, z);
+        capply<J, C>(w, Ma[0], Ma[1], tw, c, q, z);
         ctile_store<T, J>(Z, b, r1_, s, c, q, z);
-        cgram_add<J>(g, z, z);
+        cgram_add<J, C>(g, z, z);
     }
     __syncthreads();
     g.store(s, reinterpret_cast<c64*>(&tiles[0][0]), part + (size_t)blockIdx.x * s * s);
 }
 
-// k_blst_upd for complex blocks: X += U (a C) + S~ (omega C); Z = S~ - omega T~;
+// Bl-BiCGStab-rQ: X += U (a C) + S~ (omega C); Z = S~ - omega T~;
 // part = Z^H Z.
 template <class T, int J>
 __global__ __launch_bounds__(kBlock) void k_blst_updc(const Ctl* ctl, Tile16 tl, const c64* __restrict__ mats,
@@ -303,6 +312,7 @@ __global__ __launch_bounds__(kBlock) void k_blst_updc(const Ctl* ctl, Tile16 tl,
                                                       const T* __restrict__ U, const T* __restrict__ St,
                                                       const T* __restrict__ Tt, T* __restrict__ Z, c64* part) {
     if (stopped(ctl)) return;
+    constexpr bool C = Tr<T>::cplx;
     constexpr int S = 16 * J, LD = cld<J>();
     const int s = tl.s;
     __shared__ double Mac[2][S * LD];   // a C
@@ -314,7 +324,7 @@ __global__ __launch_bounds__(kBlock) void k_blst_updc(const Ctl* ctl, Tile16 tl,
     const c64 mw = -sc[SC_OMEGA];
     SKR_CTILE_RANGE(tl);
     double* tw = tiles[w_];
-    GramAcc<J, true> g;
+    GramAcc<J, C> g;
     g.clear();
     for (int b = r0_ + 16 * w_; b < r1_; b += 16 * kWaves) {
         CTile<J> u, st, tt, x, z;
@@ -322,8 +332,8 @@ __global__ __launch_bounds__(kBlock) void k_blst_updc(const Ctl* ctl, Tile16 tl,
         ctile_load<T, J>(St, b, r1_, s, c, q, st);
         ctile_load<T, J>(Tt, b, r1_, s, c, q, tt);
         ctile_load<T, J>(X, b, r1_, s, c, q, x);
-        capply<J>(u, Mac[0], Mac[1], tw, c, q, x);
-        capply<J>(st, Mwc[0], Mwc[1], tw, c, q, x);
+        capply<J, C>(u, Mac[0], Mac[1], tw, c, q, x);
+        capply<J, C>(st, Mwc[0], Mwc[1], tw, c, q, x);
         ctile_store<T, J>(X, b, r1_, s, c, q, x);
 #pragma unroll
         for (int h = 0; h < J; ++h)
@@ -334,7 +344,7 @@ __global__ __launch_bounds__(kBlock) void k_blst_updc(const Ctl* ctl, Tile16 tl,
                 z.i[h][v] = fma(mw.x, ti, fma(mw.y, tr, st.i[h][v]));
             }
         ctile_store<T, J>(Z, b, r1_, s, c, q, z);
-        cgram_add<J>(g, z, z);
+        cgram_add<J, C>(g, z, z);
     }
     __syncthreads();
     g.store(s, reinterpret_cast<c64*>(&tiles[0][0]), part + (size_t)blockIdx.x * s * s);

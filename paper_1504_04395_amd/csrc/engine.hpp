@@ -270,7 +270,7 @@ void tri_pass(Env<T>& e, int slot, int cond, int nchain, int add_shift, int mode
         else
             k_bl_tri16<T, 3, true><<<e.nb, kBlock, 0, e.st>>>(e.ctl, slot, cond, nchain, add_shift, e.tl, mode,
                                                              e.mats, Z, Out, Other, e.part);
-    } else if constexpr (Tr<T>::cplx) {
+    } else {   // complex, or real with s > 16
         const bool oth = (mode & (TRI_G_OTHER_OUT | TRI_G_OUT_OTHER)) != 0;
         if (nchain + add_shift <= 1 && !oth)
             k_bl_tric<T, J, 1, false><<<e.nb, kBlock, 0, e.st>>>(e.ctl, slot, cond, nchain, add_shift, e.tl, mode,
@@ -281,9 +281,6 @@ void tri_pass(Env<T>& e, int slot, int cond, int nchain, int add_shift, int mode
         else
             k_bl_tric<T, J, 3, true><<<e.nb, kBlock, 0, e.st>>>(e.ctl, slot, cond, nchain, add_shift, e.tl, mode,
                                                                 e.mats, Z, Out, Other, e.part);
-    } else {
-        k_bl_tri<T, J><<<e.nb, kBlock, mat_lds(e.s, 3, 1), e.st>>>(e.ctl, slot, cond, nchain, add_shift, e.tl, mode,
-                                                                    e.mats, Z, Out, Other, e.part);
     }
     SKR_LAUNCHED();
 }
@@ -319,12 +316,9 @@ void axpm(Env<T>& e, int mslot, int gslot, const T* A, const T* B, const T* C, T
     if constexpr (!Tr<T>::cplx && J == 1) {
         k_bl_axpm16<T, GRAM><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.tl, e.mats, mslot, e.sc, gslot, A, B, C, Out,
                                                         e.part);
-    } else if constexpr (Tr<T>::cplx) {
+    } else {   // complex, or real with s > 16
         k_bl_axpmc<T, J, GRAM><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.tl, e.mats, mslot, e.sc, gslot, A, B, C, Out,
                                                           e.part);
-    } else {
-        k_bl_axpm<T, J, GRAM><<<e.nb, kBlock, mat_lds(e.s, 1, 1), e.st>>>(e.ctl, e.tl, e.mats, mslot, e.sc, gslot,
-                                                                           A, B, C, Out, e.part);
     }
     SKR_LAUNCHED();
 }
@@ -332,10 +326,8 @@ template <class T, int J>
 void blrq_updz(Env<T>& e, T* X, const T* V, const T* Q, const T* W, T* Z) {
     if constexpr (!Tr<T>::cplx && J == 1) {
         k_blrq_updz16<T><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.tl, e.mats, X, V, Q, W, Z, e.part);
-    } else if constexpr (Tr<T>::cplx) {
+    } else {   // complex, or real with s > 16
         k_blrq_updzc<T, J><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.tl, e.mats, X, V, Q, W, Z, e.part);
-    } else {
-        k_blrq_updz<T, J><<<e.nb, kBlock, mat_lds(e.s, 2, 2), e.st>>>(e.ctl, e.tl, e.mats, X, V, Q, W, Z, e.part);
     }
     SKR_LAUNCHED();
 }
@@ -343,11 +335,8 @@ template <class T, int J>
 void blst_upd(Env<T>& e, T* X, const T* U, const T* St, const T* Tt, T* Z) {
     if constexpr (!Tr<T>::cplx && J == 1) {
         k_blst_upd16<T><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.tl, e.mats, e.sc, X, U, St, Tt, Z, e.part);
-    } else if constexpr (Tr<T>::cplx) {
+    } else {   // complex, or real with s > 16
         k_blst_updc<T, J><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.tl, e.mats, e.sc, X, U, St, Tt, Z, e.part);
-    } else {
-        k_blst_upd<T, J><<<e.nb, kBlock, mat_lds(e.s, 2, 2), e.st>>>(e.ctl, e.tl, e.mats, e.sc, X, U, St, Tt, Z,
-                                                                    e.part);
     }
     SKR_LAUNCHED();
 }
