@@ -193,15 +193,17 @@ void ilu0_factor(int n, const std::vector<int>& rp, const std::vector<int>& ci, 
 }
 
 // Y = T^-1 Z for one triangular operator, level by level (Y may equal Z).
-// When the levels hold on average at most two passes of one workgroup
-// (rows x s <= 2048), a single workgroup sweeps them all; otherwise each
-// level is its own launch over as many workgroups as it needs.
+// When the levels are narrow -- on average at most 256 rows (each a few
+// scattered cache lines that one CU must fetch) and at most two passes of one
+// workgroup (rows x s <= 2048) -- a single workgroup sweeps them all;
+// otherwise each level is its own launch over as many workgroups as it needs.
 template <class T>
 void tri_solve(hipStream_t st, const TriDev& t, int s, const T* Z, T* Y, const Ctl* ctl) {
     const TriOp<T> op{t.rp, t.ci, (const T*)t.va, (const T*)t.dg, t.rows};
     const int nlev = (int)t.lvl.size() - 1;
     if (nlev < 1) return;
-    if ((long long)t.lvl[nlev] * s <= 2LL * kTrsvWg * nlev) {
+    const long long rows = t.lvl[nlev];
+    if (rows <= 256LL * nlev && rows * s <= 2LL * kTrsvWg * nlev) {
         k_trsv_wg<T><<<1, kTrsvWg, 0, st>>>(ctl, op, t.dlvl, nlev, s, Z, Y);
         return;
     }
