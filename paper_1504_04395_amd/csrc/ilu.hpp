@@ -29,13 +29,18 @@ struct IluError {
     std::string what;
 };
 
+// A triangular operator in level order: position p = 0..n-1 runs over the rows
+// level by level; rows[p] is the row at p, and rp[p]..rp[p+1] its strictly
+// triangular entries (ci, va), dg[p] its diagonal.  The row index, the entry
+// range and the diagonal of a position are independent loads, and the entries
+// of one level are contiguous.
 template <class T>
 struct TriOp {
-    const int* rp;     // strictly triangular part, CSR
+    const int* rp;
     const int* ci;
     const T* va;
-    const T* dg;       // diagonal; nullptr = unit diagonal
-    const int* rows;   // rows ordered by level
+    const T* dg;       // nullptr = unit diagonal
+    const int* rows;
 };
 
 __device__ inline double tdiv(double a, double b) { return a / b; }
@@ -49,10 +54,10 @@ __global__ __launch_bounds__(kBlock) void k_trsv_level(const Ctl* ctl, TriOp<T> 
     const int q = (int)(g / s);
     if (q >= cnt) return;
     const int c = (int)(g - (long long)q * s);
-    const int i = F.rows[l0 + q];
+    const int p = l0 + q, i = F.rows[p];
     T acc = Z[(size_t)i * s + c];
-    for (int k = F.rp[i]; k < F.rp[i + 1]; ++k) acc = fma_(-F.va[k], Y[(size_t)F.ci[k] * s + c], acc);
-    Y[(size_t)i * s + c] = F.dg ? tdiv(acc, F.dg[i]) : acc;
+    for (int k = F.rp[p]; k < F.rp[p + 1]; ++k) acc = fma_(-F.va[k], Y[(size_t)F.ci[k] * s + c], acc);
+    Y[(size_t)i * s + c] = F.dg ? tdiv(acc, F.dg[p]) : acc;
 }
 
 // All levels in one workgroup (levels with little work): the workgroup sweeps
@@ -67,10 +72,10 @@ __global__ __launch_bounds__(kTrsvWg) void k_trsv_wg(const Ctl* ctl, TriOp<T> F,
         const int l0 = lvl[l], work = (lvl[l + 1] - l0) * s;
         for (int g = threadIdx.x; g < work; g += kTrsvWg) {
             const int q = g / s, c = g - q * s;
-            const int i = F.rows[l0 + q];
+            const int p = l0 + q, i = F.rows[p];
             T acc = Z[(size_t)i * s + c];
-            for (int k = F.rp[i]; k < F.rp[i + 1]; ++k) acc = fma_(-F.va[k], Y[(size_t)F.ci[k] * s + c], acc);
-            Y[(size_t)i * s + c] = F.dg ? tdiv(acc, F.dg[i]) : acc;
+            for (int k = F.rp[p]; k < F.rp[p + 1]; ++k) acc = fma_(-F.va[k], Y[(size_t)F.ci[k] * s + c], acc);
+            Y[(size_t)i * s + c] = F.dg ? tdiv(acc, F.dg[p]) : acc;
         }
         __syncthreads();
     }
@@ -124,6 +129,29 @@ void tri_levels(TriHost<T>& t, int n, bool forward) {
     std::vector<int> fill(t.lvl.begin(), t.lvl.end() - 1);
     t.rows.assign(n, 0);
     for (int i = 0; i < n; ++i) t.rows[fill[lev[i]]++] = i;
+}
+
+// The level-order copy of a row-ordered operator (after tri_levels): entry
+// range, entries and diagonal of the row at each position of t.rows.
+template <class T>
+void tri_level_order(const TriHost<T>& t, int n, TriHost<T>& out) {
+    out.rp.assign(n + 1, 0);
+    out.ci.clear();
+    out.va.clear();
+    out.ci.reserve(t.ci.size());
+    out.va.reserve(t.va.size());
+    if (!t.dg.empty()) out.dg.resize(n);
+    for (int p = 0; p < n; ++p) {
+        const int i = t.rows[p];
+        for (int k = t.rp[i]; k < t.rp[i + 1]; ++k) {
+            out.ci.push_back(t.ci[k]);
+            out.va.push_back(t.va[k]);
+        }
+        out.rp[p + 1] = (int)out.ci.size();
+        if (!t.dg.empty()) out.dg[p] = t.dg[i];
+    }
+    out.rows = t.rows;
+    out.lvl = t.lvl;
 }
 
 // Conjugate transpose of a strictly triangular CSR (counting sort by column).

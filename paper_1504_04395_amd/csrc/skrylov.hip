@@ -307,8 +307,11 @@ void free_ilu(skr_matrix* M) {
     M->ilu = nullptr;
 }
 
+// upload of the level-order copy of a row-ordered operator
 template <class T>
-void upload_tri(const TriHost<T>& h, int n, TriDev& d, hipStream_t st) {
+void upload_tri(const TriHost<T>& rowwise, int n, TriDev& d, hipStream_t st) {
+    TriHost<T> h;
+    tri_level_order(rowwise, n, h);
     auto up = [&](void** dst, const void* src, size_t bytes) {
         SKR_HIP(hipMalloc(dst, std::max<size_t>(bytes, 1)));
         if (bytes) SKR_HIP(hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, st));
@@ -321,6 +324,7 @@ void upload_tri(const TriHost<T>& h, int n, TriDev& d, hipStream_t st) {
     if (!h.dg.empty()) up(&d.dg, h.dg.data(), sizeof(T) * n);
     up((void**)&d.dlvl, h.lvl.data(), sizeof(int) * h.lvl.size());
     d.lvl = h.lvl;
+    SKR_HIP(hipStreamSynchronize(st));   // h is released on return
 }
 
 // ILU(0) on the host from the device CSR, level schedules, upload of L, U, U^H, L^H.

@@ -6,7 +6,9 @@
 //
 // Input:  n nnz complex(0|1) / rp[n+1] / ci[nnz] / values (re [im]) per entry
 // Output: for each of L, U, UH, LH: "name nnz nlev", rp, ci, values, diagonal
-//         (or "-"), rows (level order), level offsets.  "ERROR msg" on failure.
+//         (or "-"), rows (level order), level offsets; then the same for their
+//         level-order copies (Lo, Uo, UHo, LHo: rp, values and diagonal indexed
+//         by position).  "ERROR msg" on failure.
 #include <cstdio>
 #include <vector>
 
@@ -57,6 +59,13 @@ static int run(int n, const std::vector<int>& rp, const std::vector<int>& ci, co
     dump("U", U, n);
     dump("UH", UH, n);
     dump("LH", LH, n);
+    const TriHost<T>* ops[4] = {&L, &U, &UH, &LH};
+    const char* names[4] = {"Lo", "Uo", "UHo", "LHo"};
+    for (int k = 0; k < 4; ++k) {   // the level-order copies the device solves use
+        TriHost<T> o;
+        tri_level_order(*ops[k], n, o);
+        dump(names[k], o, n);
+    }
     return 0;
 }
 

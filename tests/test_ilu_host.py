@@ -48,7 +48,7 @@ def _run(harness, tmp_path, A):
     lines = txt.splitlines()
     ops = {}
     n = A.shape[0]
-    for b in range(4):
+    for b in range(8):
         head = lines[7 * b].split()
         name = head[0]
         rp = np.array(lines[7 * b + 1].split(), dtype=np.int64)
@@ -65,6 +65,9 @@ def _run(harness, tmp_path, A):
                 dgv = dgv[0::2] + 1j * dgv[1::2]
         rows = np.array(lines[7 * b + 5].split(), dtype=np.int64)
         lvl = np.array(lines[7 * b + 6].split(), dtype=np.int64)
+        if name.endswith("o"):   # level order: position p holds row rows[p]
+            ops[name] = (rp, ci, vals, dgv, rows, lvl)
+            continue
         T = sp.csr_array((vals, ci, rp), shape=(n, n))
         ops[name] = (T, dgv, rows, lvl)
     return ops
@@ -113,6 +116,15 @@ def test_host_ilu_matches_oracle_and_levels_are_valid(harness, tmp_path, case):
     _check_levels(U, rU, lU, False)
     _check_levels(UH, rUH, lUH, True)
     _check_levels(LH, rLH, lLH, False)
+    for nm, (T, dg, rows, lvl) in (("L", ops["L"]), ("U", ops["U"]), ("UH", ops["UH"]), ("LH", ops["LH"])):
+        rp, ci, va, dgo, rows_o, lvl_o = ops[nm + "o"]
+        assert np.array_equal(rows_o, rows) and np.array_equal(lvl_o, lvl)
+        for p_, i in enumerate(rows):
+            lo, hi = T.indptr[i], T.indptr[i + 1]
+            assert np.array_equal(ci[rp[p_]:rp[p_ + 1]], T.indices[lo:hi])
+            assert np.array_equal(va[rp[p_]:rp[p_ + 1]], T.data[lo:hi])
+        if dg is not None:
+            assert np.array_equal(dgo, dg[rows])
 
 
 def test_host_ilu_reports_missing_diagonal_and_zero_pivot(harness, tmp_path):
