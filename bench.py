@@ -181,6 +181,35 @@ def paper_table2(pkg, ctx, inputs, reps=3, examples=(1, 2, 3), preconds=(None, "
     return rows
 
 
+def config_solves(pkg, ctx, inputs, k, methods, precision, fmt, reps):
+    """Solve workload k of inputs.config (full size) with each method to 1e-8
+    (at most 3000 iterations); the best of `reps` timed solves per method."""
+    import numpy as np
+    import torch
+    prob = inputs.config(k, "full")
+    log(f"{prob.name}: n={prob.A.n} nnz={prob.A.nnz} s={prob.B.shape[1]}")
+    A = pkg.Matrix.from_csr(ctx, prob.A, fmt=fmt, make_fp32=precision != "fp64")
+    B = torch.from_numpy(np.ascontiguousarray(prob.B)).cuda()
+    X = torch.zeros_like(B)
+    kw = {} if precision == "fp64" else dict(precision=precision, inner_tol=1e-4, max_outer=20)
+    rows = []
+    for m in methods or prob.methods:
+        best = None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            _, info = pkg.solve(ctx, A, B, m, X=X, x0_zero=True, tol=1e-8, maxit=3000, **kw)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            best = dt if best is None else min(best, dt)
+        rows.append({"workload": prob.name, "format": fmt, "precision": precision, "method": m,
+                     "status": info.status_name, "iterations": info.iterations,
+                     "outer": info.outer_iterations, "rel_res_true": info.rel_res_true, "seconds": round(best, 4)})
+        log(f"{m}: {info.status_name} it={info.iterations} {best * 1e3:.1f} ms")
+    A.close()
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -206,8 +235,14 @@ def main():
                          "every method (tol 1e-10, 500 iterations), beside the paper's Table 2")
     ap.add_argument("--examples", default="1,2,3", help="with --paper-table2: which examples")
     ap.add_argument("--precond", default="none,ilu0", help="with --paper-table2: none, ilu0 or both")
-    ap.add_argument("--methods", default="", help="with --paper-table2: comma-separated subset")
-    ap.add_argument("--reps", type=int, default=3, help="with --paper-table2: solves per entry (best is kept)")
+    ap.add_argument("--methods", default="", help="with --paper-table2 or --config: comma-separated subset")
+    ap.add_argument("--reps", type=int, default=3, help="with --paper-table2 or --config: solves per entry "
+                                                          "(best is kept)")
+    ap.add_argument("--config", type=int, default=0,
+                    help="instead of the benchmark: solve workload K of inputs.config at full size with "
+                         "--methods (default: the workload's own list)")
+    ap.add_argument("--precision", default="fp64", help="with --config: fp64 or fp32_refine")
+    ap.add_argument("--format", default="csr", help="with --config: csr or sell")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is "
@@ -219,6 +254,14 @@ def main():
 
     import inputs
     import paper_1504_04395_amd as pkg
+
+    if args.config:
+        ctx = pkg.Context(0)
+        rows = config_solves(pkg, ctx, inputs, args.config, tuple(m for m in args.methods.split(",") if m),
+                             args.precision, args.format, args.reps)
+        print(json.dumps({"config_solves": rows}), flush=True)
+        ctx.close()
+        return
 
     if args.paper_table2:
         ctx = pkg.Context(0)
