@@ -2,7 +2,8 @@
 the four block methods whose stability Section 5.2 compares: Bl-BiCG,
 Bl-BiCG-rQ, Bl-BiCGStab and Bl-BiCGStab-rQ, at the paper's tolerance 1e-10
 and iteration cap 500.  Where the oracle's outcome is stable under 1e-15
-perturbations of B and of A's values, the GPU must reach it (converged:
+perturbations of B and of A's values (one to three pairs of perturbed runs,
+more only while a check against their spread fails), the GPU must reach it (converged:
 iterations within 5% plus the oracle's own spread, same X); otherwise the GPU's
 outcome (converged, stagnated at the cap, diverged, broken down) must be one
 that the oracle reaches on some perturbed input.  Plain Bl-BiCGStab on
@@ -59,37 +60,53 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
+def _spread(ref, runs):
+    """The oracle's own spread over the perturbed runs: X, iteration count, and
+    the first 8 residual-history entries."""
+    xs = max(_rel(r.X, ref.X) for r in runs)
+    its = max(abs(r.iterations - ref.iterations) for r in runs)
+    m = min([8, len(ref.history)] + [len(r.history) for r in runs])
+    hs = max(np.max(np.abs(r.history[:m] - ref.history[:m]) / ref.history[:m]) for r in runs)
+    return xs, its, hs, m
+
+
 @pytest.mark.parametrize("method", BLOCK)
 @pytest.mark.parametrize("k", [1, 2, 3])
 def test_paper_example_matches_oracle(pkg, ctx, k, method):
     prob = I.paper_example(k, "small")
     A_, B = prob.A, prob.B
     tol, maxit = 1e-10, 500
-    ref = O.solve(A_, B, method, tol=tol, maxit=maxit)
-    say(f"{prob.name} {method}: oracle {ref.status}/{ref.iterations}")
-    runs = []
-    for sd in range(3):
-        runs += _pair(A_, B, method, tol, maxit, sd)
-    xs = max(_rel(r.X, ref.X) for r in runs)
-    its = max(abs(r.iterations - ref.iterations) for r in runs)
-    m = min([8, len(ref.history)] + [len(r.history) for r in runs])
-    hs = max(np.max(np.abs(r.history[:m] - ref.history[:m]) / ref.history[:m]) for r in runs)
     M = pkg.Matrix.from_csr(ctx, A_)
     X, info = pkg.solve(ctx, M, B, method, tol=tol, maxit=maxit)
     M.close()
+    ref = O.solve(A_, B, method, tol=tol, maxit=maxit)
+    say(f"{prob.name} {method}: gpu {info.status_name}/{info.iterations}, oracle {ref.status}/{ref.iterations}")
+    # the perturbed oracle runs: one pair first, up to three while a check
+    # against the spread fails (a wider sample can only widen the spread)
+    runs = _pair(A_, B, method, tol, maxit, 0)
+    npairs = 1
+    while True:
+        xs, its, hs, m = _spread(ref, runs)
+        outcomes = {ref.status} | {r.status for r in runs}
+        mm = min(m, len(info.history))
+        hist_ok = np.all(np.abs(info.history[:mm] - ref.history[:mm]) <= max(1e-9, 100 * hs) * ref.history[:mm])
+        stable = outcomes == {O.STATUS_OK} and xs < 1e-6 and info.status == 0
+        close = (abs(info.iterations - ref.iterations) <= max(1, int(0.05 * ref.iterations)) + its
+                 and _rel(X, ref.X) <= max(1e-10, 100 * xs))
+        if (hist_ok and (not stable or close)) or npairs == 3:
+            break
+        runs += _pair(A_, B, method, tol, maxit, npairs)
+        npairs += 1
     say(f"{prob.name} {method}: gpu st={info.status_name} it={info.iterations} res={info.rel_res_true:.1e} | "
         f"oracle st={ref.status} it={ref.iterations} res={ref.rel_res_true:.1e} | ensemble "
         f"st={[r.status for r in runs]} it={[r.iterations for r in runs]} | err={_rel(X, ref.X):.1e} spread={xs:.1e}")
-    m = min(m, len(info.history))
-    np.testing.assert_allclose(info.history[:m], ref.history[:m], rtol=max(1e-9, 100 * hs), atol=0)
-    outcomes = {ref.status} | {r.status for r in runs}
-    if outcomes == {O.STATUS_OK} and xs < 1e-6 and info.status == 0:
-        assert abs(info.iterations - ref.iterations) <= max(1, int(0.05 * ref.iterations)) + its
-        assert _rel(X, ref.X) <= max(1e-10, 100 * xs)
+    np.testing.assert_allclose(info.history[:mm], ref.history[:mm], rtol=max(1e-9, 100 * hs), atol=0)
+    if stable:
+        assert close, (info.iterations, ref.iterations, its, _rel(X, ref.X), xs)
         return
     # A chaotic case: the GPU's outcome must be one the oracle itself reaches
     # under 1e-15 input perturbations.  Draw further pairs only when needed.
-    t0, sd = time.time(), 3
+    t0, sd = time.time(), npairs
     while info.status not in outcomes and sd < EXTRA_PAIRS and time.time() - t0 < EXTRA_SECONDS:
         for r in _pair(A_, B, method, tol, maxit, sd):
             outcomes.add(r.status)
