@@ -104,15 +104,24 @@ def test_block_qr(pkg, ctx, kind, s):
     assert np.allclose(np.tril(Cm, -1), 0)
 
 
-def test_block_qr_ill_conditioned_uses_shift(pkg, ctx):
+@pytest.mark.parametrize("kind,s", [("real", 8), ("real", 24), ("complex", 8), ("complex", 32)])
+def test_block_qr_ill_conditioned_uses_shift(pkg, ctx, kind, s):
+    """kappa = 1e9: the shifted first pass plus two plain passes (three inverse
+    factors applied in one final pass) on the real s <= 16 tiles and on the
+    complex / wider tiles."""
     rng = np.random.default_rng(3)
-    U, _ = np.linalg.qr(rng.standard_normal((4000, 8)))
-    Z = U @ np.diag(np.logspace(0, -9, 8)) @ np.linalg.qr(rng.standard_normal((8, 8)))[0]
-    assert np.linalg.cond(Z) > 1e8       # kappa^2 u > 1: the unshifted Cholesky of Z^T Z fails
+    cplx = kind == "complex"
+
+    def g(*shape):
+        x = rng.standard_normal(shape)
+        return x + 1j * rng.standard_normal(shape) if cplx else x
+
+    U, _ = np.linalg.qr(g(4000, s))
+    Z = U @ np.diag(np.logspace(0, -9, s)) @ np.linalg.qr(g(s, s))[0]
+    assert np.linalg.cond(Z) > 1e8       # kappa^2 u > 1: the unshifted Cholesky of Z^H Z fails
     Q, Cm, rc = pkg.block_qr(ctx, Z)
     assert rc == 0
-    # the shifted first pass plus two plain passes keep Q orthonormal
-    np.testing.assert_allclose(Q.T @ Q, np.eye(8), atol=1e-12)
+    np.testing.assert_allclose(Q.conj().T @ Q, np.eye(s), atol=1e-12)
     np.testing.assert_allclose(Q @ Cm, Z, atol=1e-13)
 
 
