@@ -81,6 +81,78 @@ __global__ __launch_bounds__(kTrsvWg) void k_trsv_wg(const Ctl* ctl, TriOp<T> F,
     }
 }
 
+// The same sweep, software-pipelined, when every level fits one pass of the
+// workgroup (rows x s <= kTrsvWg): thread t owns item t of each level (row
+// t / s of the level, column t % s).  While level l is solved, the row index,
+// entry range and diagonal of level l + 2 and the first kTrsvK entries and the
+// right-hand side of level l + 1 are already loading, so a level waits on one
+// round of memory (the gathers of solved rows) instead of three.  Prefetched
+// values are only of the operator and of Z; Z's row i is not written before
+// row i itself is solved (in-place solves included).
+constexpr int kTrsvK = 4;
+template <class T>
+struct TrsvItem {
+    bool on;
+    int i, kb, ke;
+    T d;
+};
+template <class T>
+__device__ inline TrsvItem<T> trsv_stage_a(const TriOp<T>& F, const int* __restrict__ lvl, int nlev, int l, int s,
+                                           int t) {
+    TrsvItem<T> it{false, 0, 0, 0, zero<T>()};
+    if (l >= nlev) return it;
+    const int l0 = lvl[l];
+    if (t >= (lvl[l + 1] - l0) * s) return it;
+    const int p = l0 + t / s;
+    it.on = true;
+    it.i = F.rows[p];
+    it.kb = F.rp[p];
+    it.ke = F.rp[p + 1];
+    if (F.dg) it.d = F.dg[p];
+    return it;
+}
+template <class T>
+__global__ __launch_bounds__(kTrsvWg) void k_trsv_wgp(const Ctl* ctl, TriOp<T> F, const int* __restrict__ lvl,
+                                                      int nlev, int s, const T* Z, T* Y) {
+    if (stopped(ctl)) return;
+    const int t = threadIdx.x, c = t % s;
+    int cc0[kTrsvK], cc1[kTrsvK];
+    T vv0[kTrsvK], vv1[kTrsvK], z0 = zero<T>(), z1 = zero<T>();
+    auto stage_b = [&](const TrsvItem<T>& it, int (&cc)[kTrsvK], T (&vv)[kTrsvK], T& z) {
+#pragma unroll
+        for (int k = 0; k < kTrsvK; ++k) {
+            const bool ok = it.on && it.kb + k < it.ke;
+            cc[k] = ok ? F.ci[it.kb + k] : 0;
+            vv[k] = ok ? F.va[it.kb + k] : zero<T>();
+        }
+        if (it.on) z = Z[(size_t)it.i * s + c];
+    };
+    TrsvItem<T> a0 = trsv_stage_a(F, lvl, nlev, 0, s, t);
+    stage_b(a0, cc0, vv0, z0);
+    TrsvItem<T> a1 = trsv_stage_a(F, lvl, nlev, 1, s, t);
+    for (int l = 0; l < nlev; ++l) {
+        stage_b(a1, cc1, vv1, z1);                                  // level l + 1
+        const TrsvItem<T> a2 = trsv_stage_a(F, lvl, nlev, l + 2, s, t);   // level l + 2
+        if (a0.on) {                                                // level l
+            T acc = z0;
+#pragma unroll
+            for (int k = 0; k < kTrsvK; ++k)
+                if (a0.kb + k < a0.ke) acc = fma_(-vv0[k], Y[(size_t)cc0[k] * s + c], acc);
+            for (int k = a0.kb + kTrsvK; k < a0.ke; ++k) acc = fma_(-F.va[k], Y[(size_t)F.ci[k] * s + c], acc);
+            Y[(size_t)a0.i * s + c] = F.dg ? tdiv(acc, a0.d) : acc;
+        }
+        __syncthreads();
+        a0 = a1;
+        a1 = a2;
+        z0 = z1;
+#pragma unroll
+        for (int k = 0; k < kTrsvK; ++k) {
+            cc0[k] = cc1[k];
+            vv0[k] = vv1[k];
+        }
+    }
+}
+
 // ------------------------------------------------------------------ host side
 inline bool hzero(double v) { return v == 0.0; }
 inline bool hzero(c64 v) { return v.x == 0.0 && v.y == 0.0; }
@@ -102,6 +174,7 @@ struct TriDev {
     int *rp = nullptr, *ci = nullptr, *rows = nullptr, *dlvl = nullptr;
     void *va = nullptr, *dg = nullptr;
     std::vector<int> lvl;   // level offsets into rows (host copy, drives the launches; dlvl on the device)
+    int maxrows = 0;        // rows of the widest level
     size_t bytes = 0;
 };
 
@@ -232,7 +305,10 @@ void tri_solve(hipStream_t st, const TriDev& t, int s, const T* Z, T* Y, const C
     if (nlev < 1) return;
     const long long rows = t.lvl[nlev];
     if (rows <= 256LL * nlev && rows * s <= 2LL * kTrsvWg * nlev) {
-        k_trsv_wg<T><<<1, kTrsvWg, 0, st>>>(ctl, op, t.dlvl, nlev, s, Z, Y);
+        if ((long long)t.maxrows * s <= kTrsvWg)
+            k_trsv_wgp<T><<<1, kTrsvWg, 0, st>>>(ctl, op, t.dlvl, nlev, s, Z, Y);
+        else
+            k_trsv_wg<T><<<1, kTrsvWg, 0, st>>>(ctl, op, t.dlvl, nlev, s, Z, Y);
         return;
     }
     for (size_t l = 0; l + 1 < t.lvl.size(); ++l) {

@@ -324,6 +324,8 @@ void upload_tri(const TriHost<T>& rowwise, int n, TriDev& d, hipStream_t st) {
     if (!h.dg.empty()) up(&d.dg, h.dg.data(), sizeof(T) * n);
     up((void**)&d.dlvl, h.lvl.data(), sizeof(int) * h.lvl.size());
     d.lvl = h.lvl;
+    d.maxrows = 0;
+    for (size_t l = 0; l + 1 < h.lvl.size(); ++l) d.maxrows = std::max(d.maxrows, h.lvl[l + 1] - h.lvl[l]);
     SKR_HIP(hipStreamSynchronize(st));   // h is released on return
 }
 
