@@ -45,7 +45,7 @@ typedef enum {
     SKR_E_INVALID = -1,       /* bad argument (size, pointer, NaN in input, ...) */
     SKR_E_ALLOC = -2,         /* device memory allocation failed */
     SKR_E_HIP = -3,           /* a HIP runtime call failed */
-    SKR_E_UNSUPPORTED = -4,   /* valid request this build does not provide */
+    SKR_E_UNSUPPORTED = -4,   /* valid request the library does not provide  */
     SKR_NOT_CONVERGED = 1,    /* maxit reached; X holds the last iterate */
     SKR_BREAKDOWN = 2,        /* a denominator vanished / an s x s matrix was singular */
     SKR_DIVERGED = 3          /* final true relative residual > 1 (Section 5.2, "div.") */

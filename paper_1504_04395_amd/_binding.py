@@ -78,13 +78,13 @@ _lib = None
 
 
 def load_library(path: str = LIB_PATH):
-    """Load libskrylov.so (built by ``__graft_entry__.build()``).  Raises if the
+    """Load libskrylov.so (built by ``python -m paper_1504_04395_amd.build``).  Raises if the
     library is missing: there is no fallback implementation."""
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
-        raise RuntimeError(f"HIP library not built: {path} is missing (run __graft_entry__.build())")
+        raise RuntimeError(f"HIP library not built: {path} is missing (run python -m paper_1504_04395_amd.build)")
     lib = ctypes.CDLL(path)
     for name, (res, args) in _SIGS.items():
         fn = getattr(lib, name)
