@@ -10,9 +10,12 @@ this package imports nothing from the GPU path; the two share only the seeded
 input generators in ``inputs/``.
 
 Pins (what fixes each function independently of itself) are the ``-m "not gpu"``
-tests under ``tests/test_oracle_*.py``.  Parity unpinned: Bl-BiCGStab-rQ beyond
-its s = 1 reduction and its exact-arithmetic equivalence with block BiCGStab
-(the paper does not write this variant out; see ``krylov.bl_bicgstab_rq``).
+tests under ``tests/test_oracle_*.py``.  Bl-BiCGStab-rQ, which the paper does not
+write out (its step order is a reading, see ``krylov.bl_bicgstab_rq``), is pinned
+by its s = 1 reduction to scipy's bicgstab, by equality with block BiCGStab
+(El Guennouni et al.) over the first iterations, and by its residual equalling
+psi_k(A) applied to the block BiCG residual, block BiCG itself being pinned by
+brute-force Petrov-Galerkin conditions.
 """
 from .krylov import (  # noqa: F401
     METHODS, PIN_METHODS, Result, solve, qr_pos, tr,
