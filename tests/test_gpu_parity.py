@@ -307,3 +307,28 @@ def test_graph_and_eager_agree(pkg, ctx):
         assert i1.iterations == i2.iterations == i3.iterations
         assert np.array_equal(X1, X2) and np.array_equal(X1, X3)
     A.close()
+
+
+# ---------------------------------------------------------------- awkward block widths
+@pytest.mark.parametrize("kind,s", [("real", 20), ("real", 31), ("complex", 17), ("complex", 25)])
+@pytest.mark.parametrize("method", ["bl_bicg_rq", "bl_bicgstab_rq"])
+def test_block_methods_at_odd_widths(pkg, ctx, kind, s, method):
+    """Widths that leave padding columns in the MFMA row tiles (s not a multiple
+    of 16) on a row count that leaves a ragged last tile: five iterations
+    against the oracle."""
+    if kind == "real":
+        Acsr = I.convdiff2d(37, (20.0, 20.0))                      # n = 1369
+    else:
+        Acsr = I.powerlaw(1500 + 7, seed=5, lo=4, hi=30, mean=8.0)
+    B = I.gaussian_block(Acsr.n, s, seed=s, complex_=(kind == "complex"))
+    it = 5
+    ref = O.solve(Acsr, B, method, tol=0.0, maxit=it)
+    spread, hs, _ = _self_sensitivity(Acsr, B, method, ref, tol=0.0, maxit=it)
+    A = pkg.Matrix.from_csr(ctx, Acsr)
+    X, info = pkg.solve(ctx, A, B, method, tol=0.0, maxit=it)
+    A.close()
+    err = _rel(X, ref.X)
+    print(f"{method} {kind} s={s} n={Acsr.n}: err={err:.2e} spread={spread:.2e}", flush=True)
+    assert info.status == ref.status and info.iterations == it
+    assert err < max(1e-10, 100 * spread)
+    np.testing.assert_allclose(info.history, ref.history, rtol=max(1e-9, 100 * hs.max()), atol=0)
