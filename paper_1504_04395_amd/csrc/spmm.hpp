@@ -313,13 +313,44 @@ __global__ __launch_bounds__(kBlock) void k_spmm_csr8(const Ctl* ctl, CsrOp<T> A
     const int xcd = blockIdx.x & 7, q = blockIdx.x >> 3, nq = gridDim.x >> 3;
     const int r0 = xcd * rows_per_xcd;
     const int r1 = min(A.n, r0 + rows_per_xcd);
+    const int step = nq * 64;
     const bool colok = 2 * l8 < s;          // s is even: both of the lane's columns exist, or neither
     const int cofs = colok ? 2 * l8 : 0;
     __shared__ T tiles[EPI ? kWaves : 1][EPI ? 16 * 17 : 1];
     typename Epi::St st;
     epi.init(st);
     const int tc = threadIdx.x & 15, tq = (threadIdx.x >> 4) & 3;   // tile-16 layout of the epilogue
-    for (int base = r0 + q * 64; base < r1; base += nq * 64) {
+    // Software pipeline over the wave's 16-row steps: the next step's row
+    // pointers, and then its first U entries per row, are loaded while this
+    // step's X gathers are in flight, so a step waits on one round of memory
+    // instead of three.  Rows, entries and the order of the sums are those of
+    // the plain sweep, so the result is the same to the bit.
+    auto rows_of = [&](int base, int (&i)[2], bool (&valid)[2], int (&k0)[2], int (&k1)[2]) {
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            i[p] = base + 16 * w + 8 * p + 2 * g + half;
+            valid[p] = i[p] < r1;
+            k0[p] = valid[p] ? A.rp[i[p]] : 0;
+            k1[p] = valid[p] ? A.rp[i[p] + 1] : 0;
+        }
+    };
+    auto entries = [&](const int (&k0)[2], const int (&k1)[2], int off, int (&mc)[2], T (&ma)[2]) {
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const int k = k0[p] + off + l8;
+            const int kc = max(0, min(k, k1[p] - 1));   // clamped: always a valid entry
+            mc[p] = __builtin_nontemporal_load(&A.ci[kc]);
+            const T v = __builtin_nontemporal_load(&A.va[kc]);
+            ma[p] = k < k1[p] ? v : T(0);
+        }
+    };
+    int i[2], k0[2], k1[2], mc[2];
+    bool valid[2];
+    T ma[2];
+    int base = r0 + q * 64;
+    rows_of(base, i, valid, k0, k1);
+    entries(k0, k1, 0, mc, ma);
+    for (; base < r1; base += step) {
         const int wb = base + 16 * w;
         double zp[4] = {0.0, 0.0, 0.0, 0.0};
         if constexpr (G1 || G2) {   // the Gram's other operand, loaded before the product
@@ -331,29 +362,15 @@ __global__ __launch_bounds__(kBlock) void k_spmm_csr8(const Ctl* ctl, CsrOp<T> A
                 zp[v] = ok ? zz : 0.0;
             }
         }
-        int i[2], k0[2], k1[2];
-        bool valid[2];
-#pragma unroll
-        for (int p = 0; p < 2; ++p) {
-            i[p] = wb + 8 * p + 2 * g + half;
-            valid[p] = i[p] < r1;
-            k0[p] = valid[p] ? A.rp[i[p]] : 0;
-            k1[p] = valid[p] ? A.rp[i[p] + 1] : 0;
-        }
+        int ni[2], nk0[2], nk1[2], nmc[2];
+        bool nvalid[2];
+        T nma[2];
+        rows_of(base + step, ni, nvalid, nk0, nk1);       // next step's row pointers
         double ax[2] = {0.0, 0.0}, ay[2] = {0.0, 0.0};   // FP64 accumulation, also for FP32 data
         for (int off = 0;; off += U) {
-            int mc[2];
-            T ma[2];
             int more = 0;
 #pragma unroll
-            for (int p = 0; p < 2; ++p) {
-                const int k = k0[p] + off + l8;
-                const int kc = max(0, min(k, k1[p] - 1));   // clamped: always a valid entry
-                mc[p] = __builtin_nontemporal_load(&A.ci[kc]);
-                const T v = __builtin_nontemporal_load(&A.va[kc]);
-                ma[p] = k < k1[p] ? v : T(0);
-                more |= k0[p] + off + U < k1[p];
-            }
+            for (int p = 0; p < 2; ++p) more |= k0[p] + off + U < k1[p];
             more = __any(more);
 #pragma unroll
             for (int p = 0; p < 2; ++p) {
@@ -368,7 +385,9 @@ __global__ __launch_bounds__(kBlock) void k_spmm_csr8(const Ctl* ctl, CsrOp<T> A
                     ay[p] = fma((double)a, (double)xv.y, ay[p]);
                 });
             }
+            if (off == 0) entries(nk0, nk1, 0, nmc, nma);   // next step's first entries
             if (!more) break;
+            entries(k0, k1, off + U, mc, ma);                // rows longer than U: the rest in place
         }
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
@@ -404,6 +423,15 @@ __global__ __launch_bounds__(kBlock) void k_spmm_csr8(const Ctl* ctl, CsrOp<T> A
                 }
             }
             __builtin_amdgcn_wave_barrier();
+        }
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            i[p] = ni[p];
+            valid[p] = nvalid[p];
+            k0[p] = nk0[p];
+            k1[p] = nk1[p];
+            mc[p] = nmc[p];
+            ma[p] = nma[p];
         }
     }
     epi_finish<Epi, 1>(epi, st, blockIdx.x, s);
