@@ -307,6 +307,9 @@ __global__ __launch_bounds__(kBlock) void k_spmm_csr8(const Ctl* ctl, CsrOp<T> A
     constexpr bool EPI = !std::is_same<Epi, EpiNone>::value;
     constexpr bool G1 = std::is_same<Epi, EpiGram<T, 1>>::value;        // Z^H Y
     constexpr bool G2 = std::is_same<Epi, EpiGramOmega<T, 1>>::value;   // (Y^H Z, Y^H Y)
+    constexpr bool TR = std::is_same<Epi, EpiTrace<T>>::value;          // tr(Z^H Y)
+    constexpr bool TO = std::is_same<Epi, EpiTraceOmega<T>>::value;     // (tr(Y^H Z), tr(Y^H Y))
+    constexpr bool VS = std::is_same<Epi, EpiVecSum<T>>::value;         // z^H Y 1
     const int s = ly.s;
     const int lane = threadIdx.x & 15, half = lane >> 3, l8 = lane & 7;
     const int w = threadIdx.x >> 6, g = (threadIdx.x >> 4) & 3;
@@ -352,14 +355,19 @@ __global__ __launch_bounds__(kBlock) void k_spmm_csr8(const Ctl* ctl, CsrOp<T> A
     entries(k0, k1, 0, mc, ma);
     for (; base < r1; base += step) {
         const int wb = base + 16 * w;
-        double zp[4] = {0.0, 0.0, 0.0, 0.0};
-        if constexpr (G1 || G2) {   // the Gram's other operand, loaded before the product
+        // The epilogue's second operand at the tile entry (wb + 4v + tq, tc), loaded
+        // before the product so that its latency hides behind the gathers.  Rows
+        // past the end read row `base` (< r1) instead and are zeroed.
+        T zp[4] = {T(0), T(0), T(0), T(0)};
+        if constexpr (G1 || G2 || TR || TO || VS) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int r = wb + 4 * v + tq;
                 const bool ok = r < r1 && tc < s;
-                const double zz = (double)epi.Z[(size_t)(ok ? r : wb) * s + (ok ? tc : 0)];
-                zp[v] = ok ? zz : 0.0;
+                T zz;
+                if constexpr (VS) zz = epi.z[ok ? r : base];
+                else zz = epi.Z[(size_t)(ok ? r : base) * s + (ok ? tc : 0)];
+                zp[v] = ok ? zz : T(0);
             }
         }
         int ni[2], nk0[2], nk1[2], nmc[2];
@@ -410,13 +418,22 @@ __global__ __launch_bounds__(kBlock) void k_spmm_csr8(const Ctl* ctl, CsrOp<T> A
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int lr = 4 * v + tq;
+                const bool ok = wb + lr < r1 && tc < s;
                 if constexpr (G1) {
-                    const double zv[1] = {zp[v]}, yv[1] = {(double)tw[lr * 17 + tc]};
+                    const double zv[1] = {(double)zp[v]}, yv[1] = {(double)tw[lr * 17 + tc]};
                     st.g.add(zv, yv);
                 } else if constexpr (G2) {
-                    const double zv[1] = {zp[v]}, yv[1] = {(double)tw[lr * 17 + tc]};
+                    const double zv[1] = {(double)zp[v]}, yv[1] = {(double)tw[lr * 17 + tc]};
                     st.g1.add(yv, zv);
                     st.g2.add(yv, yv);
+                } else if constexpr (TR || VS) {   // the same sums, in the same order, as their row()
+                    if (ok) dot_acc(st.acc[0], zp[v], tw[lr * 17 + tc]);
+                } else if constexpr (TO) {
+                    const T y = tw[lr * 17 + tc];
+                    if (ok) {
+                        dot_acc(st.acc[0], y, zp[v]);
+                        dot_acc(st.acc[1], y, y);
+                    }
                 } else {
                     const T y[1] = {tw[lr * 17 + tc]};
                     epi.row(st, wb + lr, wb + lr < r1, tc, l16, y);
