@@ -317,9 +317,11 @@ __global__ __launch_bounds__(kBlock) void k_spmm_csr8(const Ctl* ctl, CsrOp<T> A
     const int r0 = xcd * rows_per_xcd;
     const int r1 = min(A.n, r0 + rows_per_xcd);
     const int step = nq * 64;
+    constexpr bool DIRECT = TR || TO || VS;   // sums over rows: taken in the product's own lane layout
+    constexpr bool TILE = EPI && !DIRECT;     // the Grams read the result back as 16 x 16 tiles
     const bool colok = 2 * l8 < s;          // s is even: both of the lane's columns exist, or neither
     const int cofs = colok ? 2 * l8 : 0;
-    __shared__ T tiles[EPI ? kWaves : 1][EPI ? 16 * 17 : 1];
+    __shared__ T tiles[TILE ? kWaves : 1][TILE ? 16 * 17 : 1];
     typename Epi::St st;
     epi.init(st);
     const int tc = threadIdx.x & 15, tq = (threadIdx.x >> 4) & 3;   // tile-16 layout of the epilogue
@@ -355,19 +357,34 @@ __global__ __launch_bounds__(kBlock) void k_spmm_csr8(const Ctl* ctl, CsrOp<T> A
     entries(k0, k1, 0, mc, ma);
     for (; base < r1; base += step) {
         const int wb = base + 16 * w;
-        // The epilogue's second operand at the tile entry (wb + 4v + tq, tc), loaded
-        // before the product so that its latency hides behind the gathers.  Rows
-        // past the end read row `base` (< r1) instead and are zeroed.
+        // The epilogue's second operand is loaded before the product, so that its
+        // latency hides behind the gathers; rows past the end read row `base`
+        // (< r1) instead and are zeroed.  Grams: at the tile entry
+        // (wb + 4v + tq, tc).  Row sums: at the lane's own rows and columns.
         T zp[4] = {T(0), T(0), T(0), T(0)};
-        if constexpr (G1 || G2 || TR || TO || VS) {
+        if constexpr (G1 || G2) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int r = wb + 4 * v + tq;
                 const bool ok = r < r1 && tc < s;
-                T zz;
-                if constexpr (VS) zz = epi.z[ok ? r : base];
-                else zz = epi.Z[(size_t)(ok ? r : base) * s + (ok ? tc : 0)];
+                const T zz = epi.Z[(size_t)(ok ? r : base) * s + (ok ? tc : 0)];
                 zp[v] = ok ? zz : T(0);
+            }
+        }
+        P2 zd[2];
+        if constexpr (DIRECT) {
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                const bool ok = valid[p] && colok;
+                const int r = ok ? i[p] : base;
+                if constexpr (VS) {
+                    const T zz = epi.z[r];
+                    zd[p].x = ok ? zz : T(0);
+                } else {
+                    const P2 zz = *reinterpret_cast<const P2*>(epi.Z + (size_t)r * s + cofs);
+                    zd[p].x = ok ? zz.x : T(0);
+                    zd[p].y = ok ? zz.y : T(0);
+                }
             }
         }
         int ni[2], nk0[2], nk1[2], nmc[2];
@@ -405,7 +422,27 @@ __global__ __launch_bounds__(kBlock) void k_spmm_csr8(const Ctl* ctl, CsrOp<T> A
                 __builtin_nontemporal_store((T)ay[p], yr + 1);
             }
         }
-        if constexpr (EPI) {
+        if constexpr (DIRECT) {
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                if (valid[p] && colok) {
+                    const T y0 = (T)ax[p], y1 = (T)ay[p];   // the stored (rounded) values
+                    if constexpr (VS) {
+                        dot_acc(st.acc[0], zd[p].x, y0);
+                        dot_acc(st.acc[0], zd[p].x, y1);
+                    } else if constexpr (TR) {
+                        dot_acc(st.acc[0], zd[p].x, y0);
+                        dot_acc(st.acc[0], zd[p].y, y1);
+                    } else {
+                        dot_acc(st.acc[0], y0, zd[p].x);
+                        dot_acc(st.acc[1], y0, y0);
+                        dot_acc(st.acc[0], y1, zd[p].y);
+                        dot_acc(st.acc[1], y1, y1);
+                    }
+                }
+            }
+        }
+        if constexpr (TILE) {
             T* tw = tiles[w];
 #pragma unroll
             for (int p = 0; p < 2; ++p) {
@@ -418,7 +455,6 @@ __global__ __launch_bounds__(kBlock) void k_spmm_csr8(const Ctl* ctl, CsrOp<T> A
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int lr = 4 * v + tq;
-                const bool ok = wb + lr < r1 && tc < s;
                 if constexpr (G1) {
                     const double zv[1] = {(double)zp[v]}, yv[1] = {(double)tw[lr * 17 + tc]};
                     st.g.add(zv, yv);
@@ -426,14 +462,6 @@ __global__ __launch_bounds__(kBlock) void k_spmm_csr8(const Ctl* ctl, CsrOp<T> A
                     const double zv[1] = {(double)zp[v]}, yv[1] = {(double)tw[lr * 17 + tc]};
                     st.g1.add(yv, zv);
                     st.g2.add(yv, yv);
-                } else if constexpr (TR || VS) {   // the same sums, in the same order, as their row()
-                    if (ok) dot_acc(st.acc[0], zp[v], tw[lr * 17 + tc]);
-                } else if constexpr (TO) {
-                    const T y = tw[lr * 17 + tc];
-                    if (ok) {
-                        dot_acc(st.acc[0], y, zp[v]);
-                        dot_acc(st.acc[1], y, y);
-                    }
                 } else {
                     const T y[1] = {tw[lr * 17 + tc]};
                     epi.row(st, wb + lr, wb + lr < r1, tc, l16, y);
