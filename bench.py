@@ -210,6 +210,47 @@ def config_solves(pkg, ctx, inputs, k, methods, precision, fmt, reps):
     return rows
 
 
+def sell_sweep(pkg, ctx, inputs, stream, reps=20):
+    """Sparse x block product on the power-law workload (complex, s = 32, 2^20
+    rows with lengths 4..400): CSR, and SELL-C-sigma for C in {16, 32, 64} and
+    sigma in {C, 256, 1024, 8192}, each with its padding ratio (stored slots /
+    nnz) and the average kernel time from HIP events on the context's stream."""
+    import numpy as np
+    import torch
+    prob = inputs.config(4, "full")
+    log(f"{prob.name}: n={prob.A.n} nnz={prob.A.nnz} s={prob.B.shape[1]}")
+    X = torch.from_numpy(np.ascontiguousarray(prob.B)).cuda()
+    Y = torch.empty_like(X)
+    torch.cuda.synchronize()
+
+    def timed(A):
+        with torch.cuda.stream(stream):
+            for _ in range(3):
+                pkg.spmm(ctx, A, X, Y, sync=False)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                pkg.spmm(ctx, A, X, Y, sync=False)
+            e1.record(stream)
+        e1.synchronize()
+        return round(e0.elapsed_time(e1) * 1e3 / reps, 1)
+
+    rows = []
+    A = pkg.Matrix.from_csr(ctx, prob.A)
+    rows.append({"format": "csr", "padding": 1.0, "us": timed(A)})
+    A.close()
+    log(f"csr: {rows[-1]['us']} us")
+    for C in (16, 32, 64):
+        for sigma in sorted({C, 256, 1024, 8192}):
+            A = pkg.Matrix.from_csr(ctx, prob.A, fmt="sell", sell_C=C, sell_sigma=sigma)
+            rows.append({"format": "sell", "C": C, "sigma": sigma, "padding": round(A.sell_padding, 4),
+                         "us": timed(A)})
+            A.close()
+            log(f"sell C={C} sigma={sigma}: padding {rows[-1]['padding']} {rows[-1]['us']} us")
+    return {"workload": prob.name, "n": prob.A.n, "nnz": prob.A.nnz, "s": int(prob.B.shape[1]), "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -243,6 +284,9 @@ def main():
                          "--methods (default: the workload's own list)")
     ap.add_argument("--precision", default="fp64", help="with --config: fp64 or fp32_refine")
     ap.add_argument("--format", default="csr", help="with --config: csr or sell")
+    ap.add_argument("--sell-sweep", action="store_true",
+                    help="instead of the benchmark: the sparse x block product on the power-law workload "
+                         "in CSR and SELL-C-sigma (C in 16, 32, 64; sigma in C, 256, 1024, 8192)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is "
@@ -260,6 +304,13 @@ def main():
         rows = config_solves(pkg, ctx, inputs, args.config, tuple(m for m in args.methods.split(",") if m),
                              args.precision, args.format, args.reps)
         print(json.dumps({"config_solves": rows}), flush=True)
+        ctx.close()
+        return
+
+    if args.sell_sweep:
+        stream = torch.cuda.Stream()
+        ctx = pkg.Context(0, stream=stream.cuda_stream)
+        print(json.dumps({"sell_sweep": sell_sweep(pkg, ctx, inputs, stream)}), flush=True)
         ctx.close()
         return
 

@@ -79,6 +79,37 @@ def test_spmm_matches_scipy(pkg, ctx, fmt, kind, s):
     A.close()
 
 
+def _sell_slots(indptr, C, sigma):
+    """Stored slots of SELL-C-sigma by its definition: rows sorted by length
+    (longest first) inside windows of sigma rows, chunks of C consecutive sorted
+    rows, each chunk padded to its longest row."""
+    lens = np.diff(np.asarray(indptr))
+    n = lens.size
+    order = np.concatenate([w0 + np.argsort(-lens[w0:w0 + sigma], kind="stable") for w0 in range(0, n, sigma)])
+    sl = lens[order]
+    return sum(int(sl[c:c + C].max()) * C for c in range(0, n, C))
+
+
+@pytest.mark.parametrize("C,sigma", [(16, 16), (16, 256), (64, 64), (64, 256)])
+@pytest.mark.parametrize("kind,s", [("real", 4), ("real", 16), ("complex", 12), ("complex", 32)])
+def test_sell_chunk_sizes(pkg, ctx, C, sigma, kind, s):
+    """SELL-C-sigma with C = 16 and 64 (the other tests use C = 32): products with
+    A and A^H against scipy, and the padding ratio against its definition."""
+    n = 1000 + 37
+    M = _ragged_matrix(n, kind == "complex", seed=C + s)
+    say("sell", C, sigma, kind, s)
+    A = pkg.Matrix.from_csr(ctx, M, fmt="sell", sell_C=C, sell_sigma=sigma)
+    assert A.sell_padding == pytest.approx(_sell_slots(M.indptr, C, sigma) / M.nnz, rel=0, abs=1e-12)
+    X = I.gaussian_block(n, s, seed=s + 7, complex_=(kind == "complex"))
+    Sa = M.to_scipy()
+    for adj in (False, True):
+        Y = pkg.spmm(ctx, A, X, adjoint=adj)
+        ref = (Sa.conj().T @ X) if adj else (Sa @ X)
+        scale = np.abs(Sa).max() * np.abs(X).max() * 300
+        np.testing.assert_allclose(Y, ref, rtol=0, atol=1e-14 * scale)
+    A.close()
+
+
 def test_spmm_device_tensors(pkg, ctx):
     import torch
     P = I.config(2, "small")
