@@ -143,7 +143,10 @@ const char* skr_last_error(skr_context* ctx);
  * row_ptr: n+1 int64 offsets (row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz);
  * col_idx: nnz int32 columns in [0, n), strictly increasing within a row;
  * values: nnz FP64 (SKR_F64) or interleaved complex FP64 (SKR_C64).
- * All three arrays live in `mem`.  nnz must be < 2^31.  fmt may be NULL (CSR). */
+ * All three arrays live in `mem`.  n must be in [1, 2^31 - 2^20] (the device
+ * sweeps index rows with int32 and step past the last row), nnz < 2^31.  fmt may
+ * be NULL (CSR).  A SELL copy that would need 2^31 or more stored slots gives
+ * SKR_E_UNSUPPORTED. */
 int skr_matrix_create(skr_context* ctx, int64_t n, int64_t nnz, const int64_t* row_ptr,
                       const int32_t* col_idx, const void* values, int32_t dtype, int32_t mem,
                       const skr_format_opts* fmt, skr_matrix** out);

@@ -20,6 +20,7 @@ constexpr int kBlock = 256;      // threads per workgroup for every streaming ke
 constexpr int kWaves = kBlock / 64;
 constexpr int kScalar = 64;      // one wavefront: the one-workgroup coefficient kernels
 constexpr int kMaxS = 32;        // largest block width the kernels support
+constexpr int64_t kMaxRows = (1LL << 31) - (1LL << 20);   // largest n: row sweeps step int indices past n
 
 struct c64 { double x, y; };
 struct c32 { float x, y; };

@@ -249,6 +249,8 @@ void build_sell(int n, const std::vector<int>& rp, const std::vector<int>& ci, i
         out.clen[ch] = w;
         out.cptr[ch] = (int)off;
         off += (size_t)w * C;
+        if (off > (size_t)INT32_MAX)   // slot offsets are int32 on the device
+            throw Unsupported{"the SELL-C-sigma copy would need 2^31 or more stored slots; use CSR"};
     }
     out.cptr[nch] = (int)off;
     out.ci.assign(off, 0);
@@ -947,8 +949,9 @@ int skr_matrix_create(skr_context* c, int64_t n64, int64_t nnz64, const int64_t*
                       const void* values, int32_t dtype, int32_t mem, const skr_format_opts* fmt, skr_matrix** out) {
     if (!c || !out) return SKR_E_INVALID;
     *out = nullptr;
-    if (n64 < 1 || n64 >= (1LL << 31) || nnz64 < 0 || nnz64 >= (1LL << 31))
-        return fail(c, SKR_E_INVALID, "n must be in [1, 2^31) and nnz in [0, 2^31)");
+    // the kernels' row sweeps step int row indices up to one grid stride past n
+    if (n64 < 1 || n64 > kMaxRows || nnz64 < 0 || nnz64 >= (1LL << 31))
+        return fail(c, SKR_E_INVALID, "n must be in [1, 2^31 - 2^20] and nnz in [0, 2^31)");
     if (dtype != SKR_F64 && dtype != SKR_C64) return fail(c, SKR_E_INVALID, "dtype must be SKR_F64 or SKR_C64");
     if (mem != SKR_MEM_HOST && mem != SKR_MEM_DEVICE) return fail(c, SKR_E_INVALID, "bad mem");
     if (!row_ptr || (nnz64 > 0 && (!col_idx || !values))) return fail(c, SKR_E_INVALID, "null array");

@@ -316,6 +316,20 @@ def test_nan_input_rejected(pkg, ctx):
     A.close()
 
 
+def test_matrix_create_rejects_sizes_out_of_range(pkg, ctx):
+    """Rejected before any array is read: n = 0, n above 2^31 - 2^20 (the row
+    sweeps step int32 row indices past n), and SELL with C outside {16, 32, 64}."""
+    rp = np.zeros(2, dtype=np.int64)
+    ci = np.zeros(0, dtype=np.int32)
+    va = np.zeros(0)
+    for n in (0, 2**31 - 2**20 + 1, 2**31):
+        with pytest.raises(pkg.SkrError, match="n must be in"):
+            pkg.Matrix(ctx, n, rp, ci, va)
+    with pytest.raises(pkg.SkrError, match="SELL needs C"):
+        pkg.Matrix(ctx, 1, np.array([0, 1]), np.array([0], dtype=np.int32), np.ones(1), fmt="sell", sell_C=8,
+                   sell_sigma=64)
+
+
 def test_warm_start(pkg, ctx):
     C = I.convdiff2d(16)
     B = I.gaussian_block(C.n, 3, seed=2)
