@@ -520,6 +520,32 @@ def test_sddmm_oracle():
 # solution of Example 2/3's first right-hand side, and the corner data of
 # Example 1 summing to constant boundary data
 # ---------------------------------------------------------------------------
+def _table2():
+    rows = []
+    for line in open(os.path.join(GOLDEN, "table2_iterations.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        ex, pc, method, it = line.split()
+        rows.append((int(ex), None if pc == "none" else pc, method, int(it)))
+    return rows
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("row", _table2(), ids=lambda r: f"ex{r[0]}-{r[1] or 'none'}-{r[2]}")
+def test_table2_iteration_counts(row):
+    """The oracle on Examples 1-3 at full size reaches the 1e-10 reduction in
+    about the iteration count the paper prints (its discretisation and right-hand
+    sides are our reading, so the counts agree up to a few iterations)."""
+    ex, pc, method, printed = row
+    P = I.paper_example(ex)
+    r = O.solve(P.A, P.B, method, tol=1e-10, maxit=500, precond=pc)
+    assert r.status == 0, (row, r.status)
+    assert abs(r.iterations - printed) <= max(3, 0.08 * printed), (row, r.iterations)
+    # the iterate itself, not only the recursive residual (Table 2 prints 2e-11 .. 3e-10)
+    true = np.linalg.norm(P.B - P.A.to_scipy() @ r.X) / np.linalg.norm(P.B)
+    assert true < 1e-8, (row, true)
+
+
 def test_paper_examples_rho_match_table1():
     golden = {r[0]: r[3] for r in _table1()}
     for k in (1, 2, 3):
