@@ -200,8 +200,9 @@ int skr_sddmm(skr_context* ctx, const skr_matrix* A, int32_t s, const void* G, c
 /* Thin QR of an n x s block, Z = Q C with diag(C) > 0 (CholeskyQR2 on the
  * device; used for the residual QR of Section 4 and the preprocessing of
  * Section 5).  Z, Q: n x s row-major, leading dimension s, in `mem`; C: s x s
- * row-major host array.  Returns SKR_BREAKDOWN if Z is numerically rank
- * deficient even after the shifted first pass. */
+ * row-major host array.  1 <= s <= 32 and s <= n <= 2^31 - 2^20.  Returns
+ * SKR_BREAKDOWN if Z is numerically rank deficient even after the shifted
+ * first pass. */
 int skr_block_qr(skr_context* ctx, int64_t n, int32_t s, int32_t dtype, const void* Z, void* Q,
                  double* C, int32_t mem);
 

@@ -1326,8 +1326,8 @@ int skr_block_qr(skr_context* c, int64_t n64, int32_t s, int32_t dtype, const vo
                  int32_t mem) {
     if (!c) return SKR_E_INVALID;
     if (!Z || !Q || !Cout) return fail(c, SKR_E_INVALID, "null argument");
-    if (n64 < 1 || n64 >= (1LL << 31) || s < 1 || s > kMaxS || n64 < s)
-        return fail(c, SKR_E_INVALID, "need 1 <= s <= 32 and s <= n < 2^31");
+    if (n64 < 1 || n64 > kMaxRows || s < 1 || s > kMaxS || n64 < s)
+        return fail(c, SKR_E_INVALID, "need 1 <= s <= 32 and s <= n <= 2^31 - 2^20");
     if (dtype != SKR_F64 && dtype != SKR_C64) return fail(c, SKR_E_INVALID, "bad dtype");
     return guarded(c, [&]() -> int {
         SKR_HIP(hipSetDevice(c->device));
