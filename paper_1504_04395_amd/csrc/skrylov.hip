@@ -1178,6 +1178,7 @@ int skr_spmm(skr_context* c, const skr_matrix* M, int32_t s, const void* X, int6
              int32_t mem, int32_t adjoint) {
     if (!c) return SKR_E_INVALID;
     if (!M || !X || !Y) return fail(c, SKR_E_INVALID, "null argument");
+    if (M->ctx != c) return fail(c, SKR_E_INVALID, "matrix belongs to another (or a destroyed) context");
     if (s < 1 || s > kMaxS || ldx < s || ldy < s) return fail(c, SKR_E_INVALID, "bad s or leading dimension");
     return guarded(c, [&]() -> int {
         SKR_HIP(hipSetDevice(c->device));
@@ -1220,6 +1221,7 @@ int skr_spmm(skr_context* c, const skr_matrix* M, int32_t s, const void* X, int6
 int skr_matrix_ilu0(skr_context* c, skr_matrix* M) {
     if (!c) return SKR_E_INVALID;
     if (!M) return fail(c, SKR_E_INVALID, "null argument");
+    if (M->ctx != c) return fail(c, SKR_E_INVALID, "matrix belongs to another (or a destroyed) context");
     return guarded(c, [&]() -> int {
         SKR_HIP(hipSetDevice(c->device));
         hipStream_t st = c->stream();
@@ -1236,6 +1238,7 @@ int skr_precond_apply(skr_context* c, const skr_matrix* M, int32_t s, const void
                       int64_t ldy, int32_t mem, int32_t adjoint) {
     if (!c) return SKR_E_INVALID;
     if (!M || !Z || !Y) return fail(c, SKR_E_INVALID, "null argument");
+    if (M->ctx != c) return fail(c, SKR_E_INVALID, "matrix belongs to another (or a destroyed) context");
     if (!M->ilu) return fail(c, SKR_E_INVALID, "no ILU(0) factors: call skr_matrix_ilu0 first");
     if (s < 1 || s > kMaxS || ldz < s || ldy < s) return fail(c, SKR_E_INVALID, "bad s or leading dimension");
     return guarded(c, [&]() -> int {
@@ -1282,6 +1285,7 @@ int skr_sddmm(skr_context* c, const skr_matrix* M, int32_t s, const void* G, con
               double scale, int32_t mem) {
     if (!c) return SKR_E_INVALID;
     if (!M || !G || !X || !out_vals) return fail(c, SKR_E_INVALID, "null argument");
+    if (M->ctx != c) return fail(c, SKR_E_INVALID, "matrix belongs to another (or a destroyed) context");
     if (s < 1 || s > kMaxS) return fail(c, SKR_E_INVALID, "s must be in [1, 32]");
     return guarded(c, [&]() -> int {
         SKR_HIP(hipSetDevice(c->device));
