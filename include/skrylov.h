@@ -30,6 +30,9 @@
  *     skr_status from skr_solve when X holds the last iterate and the result
  *     record is filled.  Nothing aborts or throws across this interface.
  *   - Calls on one context are not thread-safe; use one context per thread.
+ *   - A matrix is used only with the context that created it; other calls get
+ *     SKR_E_INVALID.  Destroying a context leaves its matrices to be destroyed
+ *     (and unusable for anything else).
  */
 #ifndef SKRYLOV_H
 #define SKRYLOV_H

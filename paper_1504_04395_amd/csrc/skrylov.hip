@@ -1059,6 +1059,7 @@ int skr_matrix_create(skr_context* c, int64_t n64, int64_t nnz64, const int64_t*
 int skr_matrix_update_values(skr_matrix* M, const void* values, int32_t mem) {
     if (!M || !values || !M->ctx) return SKR_E_INVALID;
     skr_context* c = M->ctx;
+    if (mem != SKR_MEM_HOST && mem != SKR_MEM_DEVICE) return fail(c, SKR_E_INVALID, "bad mem");
     return guarded(c, [&]() -> int {
         SKR_HIP(hipSetDevice(c->device));
         size_t es = elt(M->dtype, false);
@@ -1180,6 +1181,7 @@ int skr_spmm(skr_context* c, const skr_matrix* M, int32_t s, const void* X, int6
     if (!M || !X || !Y) return fail(c, SKR_E_INVALID, "null argument");
     if (M->ctx != c) return fail(c, SKR_E_INVALID, "matrix belongs to another (or a destroyed) context");
     if (s < 1 || s > kMaxS || ldx < s || ldy < s) return fail(c, SKR_E_INVALID, "bad s or leading dimension");
+    if (mem != SKR_MEM_HOST && mem != SKR_MEM_DEVICE) return fail(c, SKR_E_INVALID, "bad mem");
     return guarded(c, [&]() -> int {
         SKR_HIP(hipSetDevice(c->device));
         const int n = M->n;
@@ -1241,6 +1243,7 @@ int skr_precond_apply(skr_context* c, const skr_matrix* M, int32_t s, const void
     if (M->ctx != c) return fail(c, SKR_E_INVALID, "matrix belongs to another (or a destroyed) context");
     if (!M->ilu) return fail(c, SKR_E_INVALID, "no ILU(0) factors: call skr_matrix_ilu0 first");
     if (s < 1 || s > kMaxS || ldz < s || ldy < s) return fail(c, SKR_E_INVALID, "bad s or leading dimension");
+    if (mem != SKR_MEM_HOST && mem != SKR_MEM_DEVICE) return fail(c, SKR_E_INVALID, "bad mem");
     return guarded(c, [&]() -> int {
         SKR_HIP(hipSetDevice(c->device));
         const int n = M->n;
@@ -1287,6 +1290,7 @@ int skr_sddmm(skr_context* c, const skr_matrix* M, int32_t s, const void* G, con
     if (!M || !G || !X || !out_vals) return fail(c, SKR_E_INVALID, "null argument");
     if (M->ctx != c) return fail(c, SKR_E_INVALID, "matrix belongs to another (or a destroyed) context");
     if (s < 1 || s > kMaxS) return fail(c, SKR_E_INVALID, "s must be in [1, 32]");
+    if (mem != SKR_MEM_HOST && mem != SKR_MEM_DEVICE) return fail(c, SKR_E_INVALID, "bad mem");
     return guarded(c, [&]() -> int {
         SKR_HIP(hipSetDevice(c->device));
         const int n = M->n;
@@ -1333,6 +1337,7 @@ int skr_block_qr(skr_context* c, int64_t n64, int32_t s, int32_t dtype, const vo
     if (n64 < 1 || n64 > kMaxRows || s < 1 || s > kMaxS || n64 < s)
         return fail(c, SKR_E_INVALID, "need 1 <= s <= 32 and s <= n <= 2^31 - 2^20");
     if (dtype != SKR_F64 && dtype != SKR_C64) return fail(c, SKR_E_INVALID, "bad dtype");
+    if (mem != SKR_MEM_HOST && mem != SKR_MEM_DEVICE) return fail(c, SKR_E_INVALID, "bad mem");
     return guarded(c, [&]() -> int {
         SKR_HIP(hipSetDevice(c->device));
         const int n = (int)n64;
