@@ -546,6 +546,23 @@ def test_table2_iteration_counts(row):
     assert true < 1e-8, (row, true)
 
 
+@pytest.mark.parametrize("nu", [1000.0, 10.0], ids=["ex2", "ex3"])
+@pytest.mark.parametrize("family", ["bicg", "qmr"])
+def test_p17_section53_matvec_relations(nu, family):
+    """Section 5.3's comparison of all methods: the loop-interchanged and the
+    global variant of a family need almost the same number of matrix-vector
+    products, and the economic global variant needs fewer than both (s + 1
+    instead of 2s per iteration).  Examples 2 and 3 on a 20^3 grid, s = 19."""
+    A, B = I.paper_example2(20, nu)
+    mv = {}
+    for kind in ("li", "gl", "egl"):
+        r = O.solve(A, B, f"{kind}_{family}", tol=1e-10, maxit=500)
+        assert r.status == 0, (kind, r.status)
+        mv[kind] = r.matvecs
+    assert abs(mv["li"] - mv["gl"]) <= 0.1 * mv["gl"], mv
+    assert mv["egl"] < 0.75 * min(mv["li"], mv["gl"]), mv
+
+
 def test_paper_examples_rho_match_table1():
     golden = {r[0]: r[3] for r in _table1()}
     for k in (1, 2, 3):
