@@ -563,6 +563,23 @@ def test_p17_section53_matvec_relations(nu, family):
     assert mv["egl"] < 0.75 * min(mv["li"], mv["gl"]), mv
 
 
+@pytest.mark.parametrize("family", ["bicg", "bicgstab"])
+def test_p17_block_methods_save_at_most_half(family):
+    """Section 5.3: where the block methods converge, they need fewer
+    matrix-vector products than the loop-interchanged and global methods, but
+    never fewer than half.  Example 3 on a 20^3 grid (s = 19), with the
+    QR-stabilised block variant of the family."""
+    A, B = I.paper_example2(20, 10.0)
+    mv = {}
+    for m in (f"li_{family}", f"gl_{family}", f"bl_{family}_rq"):
+        r = O.solve(A, B, m, tol=1e-10, maxit=500)
+        assert r.status == 0, (m, r.status)
+        mv[m] = r.matvecs
+    blk = mv[f"bl_{family}_rq"]
+    for other in (f"li_{family}", f"gl_{family}"):
+        assert blk < mv[other] <= 2 * blk, mv
+
+
 def test_paper_examples_rho_match_table1():
     golden = {r[0]: r[3] for r in _table1()}
     for k in (1, 2, 3):
