@@ -418,11 +418,11 @@ void refresh_values(skr_matrix* M, hipStream_t st) {
 void ensure_fp32(skr_matrix* M, hipStream_t st) {
     if (M->va32) return;
     size_t e32 = elt(M->dtype, true);
-    SKR_HIP(hipMalloc(&M->va32, std::max<size_t>(1, (size_t)M->nnz * e32)));
-    SKR_HIP(hipMalloc(&M->vaH32, std::max<size_t>(1, (size_t)M->nnz * e32)));
+    SKR_HIP(hipMalloc(&M->va32, std::max<size_t>(1, (size_t)M->nnz) * e32));
+    SKR_HIP(hipMalloc(&M->vaH32, std::max<size_t>(1, (size_t)M->nnz) * e32));
     if (M->sell) {
-        SKR_HIP(hipMalloc(&M->SA.va32, std::max<size_t>(1, M->SA.slots * e32)));
-        SKR_HIP(hipMalloc(&M->SAH.va32, std::max<size_t>(1, M->SAH.slots * e32)));
+        SKR_HIP(hipMalloc(&M->SA.va32, std::max<size_t>(1, M->SA.slots) * e32));
+        SKR_HIP(hipMalloc(&M->SAH.va32, std::max<size_t>(1, M->SAH.slots) * e32));
     }
     refresh_values(M, st);
 }
@@ -1015,8 +1015,8 @@ int skr_matrix_create(skr_context* c, int64_t n64, int64_t nnz64, const int64_t*
         M->rpH = (int*)dmalloc<int>(n + 1);
         M->ciH = (int*)dmalloc<int>(nnz);
         M->perm = (int*)dmalloc<int>(nnz);
-        SKR_HIP(hipMalloc(&M->va, std::max<size_t>(1, es * nnz)));
-        SKR_HIP(hipMalloc(&M->vaH, std::max<size_t>(1, es * nnz)));
+        SKR_HIP(hipMalloc(&M->va, es * std::max<size_t>(1, nnz)));   // at least one element
+        SKR_HIP(hipMalloc(&M->vaH, es * std::max<size_t>(1, nnz)));
         SKR_HIP(hipMemcpy(M->rp, rp.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice));
         SKR_HIP(hipMemcpy(M->rpH, rpH.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice));
         if (nnz == 0) {
@@ -1042,8 +1042,8 @@ int skr_matrix_create(skr_context* c, int64_t n64, int64_t nnz64, const int64_t*
             build_sell(n, rpH, ciH, C, sigma, hsh);
             upload_sell(M->SA, hs, C, sigma, n);
             upload_sell(M->SAH, hsh, C, sigma, n);
-            SKR_HIP(hipMalloc(&M->SA.va, std::max<size_t>(1, es * M->SA.slots)));
-            SKR_HIP(hipMalloc(&M->SAH.va, std::max<size_t>(1, es * M->SAH.slots)));
+            SKR_HIP(hipMalloc(&M->SA.va, es * std::max<size_t>(1, M->SA.slots)));
+            SKR_HIP(hipMalloc(&M->SAH.va, es * std::max<size_t>(1, M->SAH.slots)));
             M->sell_pad = nnz ? (double)M->SA.slots / nnz : 0.0;
         }
         hipStream_t st = c->stream();
