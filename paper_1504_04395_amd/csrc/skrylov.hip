@@ -19,6 +19,7 @@
 
 #include "../../include/skrylov.h"
 #include "engine.hpp"
+#include "sell.hpp"
 
 using namespace skr;
 
@@ -222,57 +223,7 @@ uint64_t fnv(const void* p, size_t n, uint64_t h = 1469598103934665603ULL) {
     return h;
 }
 
-// ---------------------------------------------------------------- SELL build (host)
-struct HostSell {
-    std::vector<int> cptr, clen, row, ci, idx;
-};
-void build_sell(int n, const std::vector<int>& rp, const std::vector<int>& ci, int C, int sigma, HostSell& out) {
-    std::vector<int> order(n);
-    for (int i = 0; i < n; ++i) order[i] = i;
-    for (int w0 = 0; w0 < n; w0 += sigma) {
-        int w1 = std::min(n, w0 + sigma);
-        std::stable_sort(order.begin() + w0, order.begin() + w1, [&](int a, int b) {
-            return (rp[a + 1] - rp[a]) > (rp[b + 1] - rp[b]);
-        });
-    }
-    int nch = (n + C - 1) / C;
-    out.cptr.assign(nch + 1, 0);
-    out.clen.assign(nch, 0);
-    out.row = order;
-    size_t off = 0;
-    for (int ch = 0; ch < nch; ++ch) {
-        int w = 0;
-        for (int r = 0; r < C && ch * C + r < n; ++r) {
-            int i = order[ch * C + r];
-            w = std::max(w, rp[i + 1] - rp[i]);
-        }
-        out.clen[ch] = w;
-        out.cptr[ch] = (int)off;
-        off += (size_t)w * C;
-        if (off > (size_t)INT32_MAX)   // slot offsets are int32 on the device
-            throw Unsupported{"the SELL-C-sigma copy would need 2^31 or more stored slots; use CSR"};
-    }
-    out.cptr[nch] = (int)off;
-    out.ci.assign(off, 0);
-    out.idx.assign(off, -1);
-    for (int ch = 0; ch < nch; ++ch) {
-        for (int r = 0; r < C; ++r) {
-            int p = ch * C + r;
-            int i = p < n ? order[p] : 0;
-            int len = p < n ? rp[i + 1] - rp[i] : 0;
-            for (int k = 0; k < out.clen[ch]; ++k) {
-                size_t e = (size_t)out.cptr[ch] + (size_t)k * C + r;
-                if (k < len) {
-                    out.ci[e] = ci[rp[i] + k];
-                    out.idx[e] = rp[i] + k;
-                } else {
-                    out.ci[e] = i;   // padding reads the row's own entry of X (value 0)
-                }
-            }
-        }
-    }
-}
-
+// ---------------------------------------------------------------- SELL upload (host build in sell.hpp)
 void upload_sell(DevSell& d, const HostSell& h, int C, int sigma, int n) {
     d.C = C;
     d.sigma = sigma;
@@ -1038,8 +989,8 @@ int skr_matrix_create(skr_context* c, int64_t n64, int64_t nnz64, const int64_t*
         if (fmtk == SKR_FMT_SELL) {
             M->sell = true;
             HostSell hs, hsh;
-            build_sell(n, rp, ci, C, sigma, hs);
-            build_sell(n, rpH, ciH, C, sigma, hsh);
+            if (!build_sell(n, rp, ci, C, sigma, hs) || !build_sell(n, rpH, ciH, C, sigma, hsh))
+                throw Unsupported{"the SELL-C-sigma copy would need 2^31 or more stored slots; use CSR"};
             upload_sell(M->SA, hs, C, sigma, n);
             upload_sell(M->SAH, hsh, C, sigma, n);
             SKR_HIP(hipMalloc(&M->SA.va, es * std::max<size_t>(1, M->SA.slots)));
