@@ -1,0 +1,87 @@
+"""CPU model of the launch geometry shared by the streaming kernels
+(csrc/engine.hpp `make_env`, csrc/common.hpp `xcd_chunk`, the row and tile
+loops of csrc/blk.hpp and csrc/glk.hpp).
+
+For ragged n and every block width it checks that
+
+  - `xcd_chunk` maps the workgroups one-to-one onto the row chunks;
+  - the chunks, the 16-row tiles each wave sweeps, the lane-group row passes
+    and the flat element loop cover every row (element) exactly once;
+  - at the largest n the matrix set-up accepts, no int32 row index formed by
+    these loops (a chunk end, a pass start one stride past the end, the 8-lane
+    SpMM's next-pass prefetch) overflows.
+
+The model restates the launch arithmetic; a change to one side must be made on
+the other.
+"""
+import numpy as np
+import pytest
+
+BLOCK = 256
+WAVES = BLOCK // 64
+MAX_ROWS = (1 << 31) - (1 << 20)      # the largest n skr_matrix_create accepts
+INT32_MAX = (1 << 31) - 1
+
+
+def env(n, s):
+    nb = (n + 63) // 64
+    nb = ((nb + 7) // 8) * 8
+    nb = max(8, min(2048, nb))
+    rpc = (n + nb - 1) // nb
+    rpc = ((rpc + 15) // 16) * 16
+    total = n * s
+    per = (total + nb - 1) // nb
+    per = ((per + BLOCK - 1) // BLOCK) * BLOCK
+    L = min(16, 1 << (s.bit_length() - 1))
+    return nb, rpc, per, total, L
+
+
+def xcd_chunk(b, nb):
+    return (b & 7) * (nb >> 3) + (b >> 3)
+
+
+@pytest.mark.parametrize("nb", [8, 16, 24, 512, 2048])
+def test_xcd_chunk_is_a_bijection(nb):
+    assert sorted(xcd_chunk(b, nb) for b in range(nb)) == list(range(nb))
+
+
+@pytest.mark.parametrize("n", [1, 15, 16, 17, 63, 64, 65, 1000, 4099, 131_072 + 5])
+@pytest.mark.parametrize("s", [1, 3, 16, 17, 32])
+def test_row_tile_and_flat_loops_cover_once(n, s):
+    nb, rpc, per, total, L = env(n, s)
+    assert rpc % 16 == 0 and nb % 8 == 0
+    tiles = np.zeros(n, dtype=np.int64)     # 16-row tiles swept by the waves (blk.hpp kernels)
+    passes = np.zeros(n, dtype=np.int64)    # SKR_ROW_LOOP lane-group passes (glk.hpp kernels)
+    flat = np.zeros(total, dtype=np.int64)  # SKR_FLAT_LOOP
+    rpb = BLOCK // L
+    for b in range(nb):
+        c = xcd_chunk(b, nb)
+        r0 = c * rpc
+        r1 = min(n, r0 + rpc)
+        for w in range(WAVES):
+            for t0 in range(r0 + 16 * w, r1, 16 * WAVES):
+                rows = t0 + np.arange(16)
+                tiles[rows[rows < r1]] += 1
+        for base in range(r0, r1, rpb):
+            rows = base + np.arange(rpb)
+            passes[rows[rows < r1]] += 1
+        e0 = c * per
+        e1 = min(e0 + per, total)
+        if e0 < e1:
+            flat[e0:e1] += 1
+    assert np.all(tiles == 1) and np.all(passes == 1) and np.all(flat == 1)
+
+
+@pytest.mark.parametrize("s", [1, 2, 16, 32])
+def test_no_int32_overflow_at_the_row_limit(s):
+    n = MAX_ROWS
+    nb, rpc, per, total, L = env(n, s)
+    # chunk ends and the first pass start past a chunk end
+    last_chunk_end = (nb - 1) * rpc + rpc
+    assert last_chunk_end + 16 * WAVES <= INT32_MAX
+    assert last_chunk_end + BLOCK <= INT32_MAX
+    # the 8-lane SpMM: rows per XCD, and the next-pass prefetch one stride past the last pass
+    per_xcd = ((n + 7) // 8 + 63) // 64 * 64
+    step = (nb >> 3) * 64
+    assert 8 * per_xcd + step + 64 <= INT32_MAX
+    assert n + step + 64 <= INT32_MAX
