@@ -85,3 +85,24 @@ def test_no_int32_overflow_at_the_row_limit(s):
     step = (nb >> 3) * 64
     assert 8 * per_xcd + step + 64 <= INT32_MAX
     assert n + step + 64 <= INT32_MAX
+
+
+@pytest.mark.parametrize("n", [1, 17, 1000, 65_536 + 9])
+@pytest.mark.parametrize("C", [16, 32, 64])
+@pytest.mark.parametrize("L", [1, 4, 16])
+def test_sell_chunk_walk_covers_every_position_once(n, C, L):
+    """k_spmm_sell: workgroup b owns chunks [xcd_chunk(b) * cpb, +cpb) and walks
+    their sorted positions in passes of BLOCK / L rows."""
+    nb, _, _, _, _ = env(n, 1)
+    nchunks = (n + C - 1) // C
+    cpb = (nchunks + nb - 1) // nb
+    rpb = BLOCK // L
+    seen = np.zeros(n, dtype=np.int64)
+    for b in range(nb):
+        cb = xcd_chunk(b, nb) * cpb
+        ce = min(nchunks, cb + cpb)
+        pb, pe = cb * C, min(n, ce * C)
+        for base in range(pb, pe, rpb):
+            p = base + np.arange(rpb)
+            seen[p[p < pe]] += 1
+    assert np.all(seen == 1)
