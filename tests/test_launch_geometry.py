@@ -85,6 +85,11 @@ def test_no_int32_overflow_at_the_row_limit(s):
     step = (nb >> 3) * 64
     assert 8 * per_xcd + step + 64 <= INT32_MAX
     assert n + step + 64 <= INT32_MAX
+    # the SELL kernel: chunk starts of the last workgroups (past the last chunk) times C
+    for C in (16, 32, 64):
+        nchunks = (n + C - 1) // C
+        cpb = (nchunks + nb - 1) // nb
+        assert ((nb - 1) * cpb + cpb) * C + BLOCK <= INT32_MAX
 
 
 @pytest.mark.parametrize("n", [1, 17, 1000, 65_536 + 9])
