@@ -111,3 +111,33 @@ def test_sell_chunk_walk_covers_every_position_once(n, C, L):
             p = base + np.arange(rpb)
             seen[p[p < pe]] += 1
     assert np.all(seen == 1)
+
+
+def _per_xcd_sweep(n, nb, per_xcd, rows_per_pass, row_of):
+    """Rows touched by a per-XCD sweep: XCD b & 7 owns rows [xcd * per_xcd, +per_xcd),
+    its workgroup q starts at q * rows_per_pass and strides by nq * rows_per_pass;
+    row_of(base) gives the rows one pass covers."""
+    seen = np.zeros(n, dtype=np.int64)
+    nq = nb >> 3
+    for b in range(nb):
+        xcd, q = b & 7, b >> 3
+        r0 = xcd * per_xcd
+        r1 = min(n, r0 + per_xcd)
+        for base in range(r0 + q * rows_per_pass, r1, nq * rows_per_pass):
+            rows = row_of(base)
+            np.add.at(seen, rows[rows < r1], 1)
+    return seen
+
+
+@pytest.mark.parametrize("n", [1, 33, 1000, 20_000 + 11])
+def test_sixteen_lane_csr_and_single_vector_sweeps_cover_once(n):
+    nb, _, _, _, _ = env(n, 16)
+    # k_spmm_csr: 16 lanes per row, RP row passes of 16 lane groups (16 rows) per pass
+    per_xcd = ((n + 7) // 8 + 31) // 32 * 32
+    for RP in (1, 2):
+        seen = _per_xcd_sweep(n, nb, per_xcd, RP * 16,
+                              lambda base: (base + 16 * np.arange(RP)[:, None] + np.arange(16)[None, :]).ravel())
+        assert np.all(seen == 1), RP
+    # k_spmv_csr: 8 lanes per row, 32 rows per pass
+    seen = _per_xcd_sweep(n, nb, per_xcd, 32, lambda base: base + np.arange(32))
+    assert np.all(seen == 1)
