@@ -19,6 +19,7 @@
 
 #include "../../include/skrylov.h"
 #include "engine.hpp"
+#include "csr_host.hpp"
 #include "sell.hpp"
 
 using namespace skr;
@@ -928,32 +929,10 @@ int skr_matrix_create(skr_context* c, int64_t n64, int64_t nnz64, const int64_t*
             SKR_HIP(hipMemcpy(rp64.data(), row_ptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost));
             if (nnz) SKR_HIP(hipMemcpy(ci.data(), col_idx, sizeof(int) * nnz, hipMemcpyDeviceToHost));
         }
-        if (rp64[0] != 0 || rp64[n] != nnz64) return fail(c, SKR_E_INVALID, "row_ptr[0] must be 0 and row_ptr[n] = nnz");
-        std::vector<int> rp(n + 1);
-        for (int i = 0; i < n; ++i) {
-            if (rp64[i + 1] < rp64[i]) return fail(c, SKR_E_INVALID, "row_ptr must be non-decreasing");
-            rp[i] = (int)rp64[i];
-            for (int64_t k = rp64[i]; k < rp64[i + 1]; ++k) {
-                int col = ci[k];
-                if (col < 0 || col >= n) return fail(c, SKR_E_INVALID, "column index out of range");
-                if (k > rp64[i] && col <= ci[k - 1])
-                    return fail(c, SKR_E_INVALID, "column indices must be strictly increasing within a row");
-            }
-        }
-        rp[n] = nnz;
-        // A^H index structure: stable counting sort by column
-        std::vector<int> rpH(n + 1, 0), ciH(nnz), perm(nnz);
-        for (int k = 0; k < nnz; ++k) rpH[ci[k] + 1]++;
-        for (int i = 0; i < n; ++i) rpH[i + 1] += rpH[i];
-        {
-            std::vector<int> next(rpH.begin(), rpH.end() - 1);
-            for (int i = 0; i < n; ++i)
-                for (int k = rp[i]; k < rp[i + 1]; ++k) {
-                    int p = next[ci[k]]++;
-                    ciH[p] = i;
-                    perm[p] = k;
-                }
-        }
+        std::vector<int> rp;
+        if (const char* why = validate_csr(n, nnz64, rp64, ci, rp)) return fail(c, SKR_E_INVALID, why);
+        std::vector<int> rpH, ciH, perm;
+        adjoint_pattern(n, rp, ci, rpH, ciH, perm);
         std::unique_ptr<skr_matrix> M(new skr_matrix());
         M->ctx = c;
         M->device = c->device;
