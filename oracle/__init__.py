@@ -15,7 +15,10 @@ write out (its step order is a reading, see ``krylov.bl_bicgstab_rq``), is pinne
 by its s = 1 reduction to scipy's bicgstab, by equality with block BiCGStab
 (El Guennouni et al.) over the first iterations, and by its residual equalling
 psi_k(A) applied to the block BiCG residual, block BiCG itself being pinned by
-brute-force Petrov-Galerkin conditions.
+brute-force Petrov-Galerkin conditions.  Values the paper prints pin the
+methods as well: the iteration counts of Table 2 (Section 5.2, Examples 1-3,
+with and without ILU(0)) and the matrix-vector product relations between the
+method families of Section 5.3.
 """
 from .krylov import (  # noqa: F401
     METHODS, PIN_METHODS, Result, solve, qr_pos, tr,
