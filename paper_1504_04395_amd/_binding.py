@@ -142,6 +142,30 @@ def _ptr_mem(x):
     return a.ctypes.data, SKR_MEM_HOST, dt, a
 
 
+def _dtype_code(x):
+    """SKR_F64 / SKR_C64 of a float64 / complex128 array or tensor, else None."""
+    if _is_torch(x):
+        import torch
+        return {torch.float64: SKR_F64, torch.complex128: SKR_C64}.get(x.dtype)
+    return {np.dtype(np.float64): SKR_F64, np.dtype(np.complex128): SKR_C64}.get(np.asarray(x).dtype)
+
+
+def _check_block(x, n: int, dt: int, name: str, like=None):
+    """Reject, before any library call, an operand whose shape or element type
+    does not match what the C call will read or write: a 2-D block of n rows
+    and 1..32 columns of A's element type, with the shape of ``like`` if given."""
+    if len(x.shape) != 2:
+        raise ValueError(f"{name} must be a 2-D n x s block")
+    if int(x.shape[0]) != n:
+        raise ValueError(f"{name} has {int(x.shape[0])} rows; the matrix has n = {n}")
+    if not 1 <= int(x.shape[1]) <= 32:
+        raise ValueError(f"{name} must have between 1 and 32 columns")
+    if _dtype_code(x) != dt:
+        raise ValueError(f"{name} must be {'complex128' if dt == SKR_C64 else 'float64'}, like the matrix")
+    if like is not None and tuple(x.shape) != tuple(like.shape):
+        raise ValueError(f"{name} must have the shape {tuple(like.shape)}")
+
+
 class Context:
     """skr_context_create / skr_context_destroy."""
 
@@ -178,6 +202,20 @@ class Matrix:
         self.ctx = ctx
         if _is_torch(data):
             import torch
+            if not (_is_torch(indptr) and _is_torch(indices)):
+                raise ValueError("indptr, indices and data must all be torch tensors, or all host arrays")
+            if indptr.dtype != torch.int64 or indices.dtype != torch.int32:
+                raise ValueError("indptr must be int64 and indices int32")
+            if data.dtype not in (torch.float64, torch.complex128):
+                raise ValueError("values must be float64 or complex128")
+            if not (indptr.device == indices.device == data.device):
+                raise ValueError("indptr, indices and data must live on the same device")
+            if not (indptr.is_contiguous() and indices.is_contiguous() and data.is_contiguous()):
+                raise ValueError("tensors must be contiguous")
+            if indptr.dim() != 1 or int(indptr.numel()) != int(n) + 1:
+                raise ValueError("indptr must have n + 1 entries")
+            if indices.dim() != 1 or data.dim() != 1 or int(indices.numel()) != int(data.numel()):
+                raise ValueError("indices and data must be 1-D with nnz entries each")
             p_rp, p_ci, p_va = indptr.data_ptr(), indices.data_ptr(), data.data_ptr()
             mem = SKR_MEM_DEVICE if data.is_cuda else SKR_MEM_HOST
             dtype = SKR_C64 if data.dtype == torch.complex128 else SKR_F64
@@ -189,6 +227,10 @@ class Matrix:
             va = np.ascontiguousarray(data)
             if va.dtype not in (np.float64, np.complex128):
                 raise ValueError("values must be float64 or complex128")
+            if rp.ndim != 1 or rp.size != int(n) + 1:
+                raise ValueError("indptr must have n + 1 entries")
+            if ci.ndim != 1 or va.ndim != 1 or ci.size < int(rp[-1]) or va.size < int(rp[-1]) or int(rp[-1]) < 0:
+                raise ValueError("indices and data must hold indptr[n] entries")
             self._keep = [rp, ci, va]
             p_rp, p_ci, p_va = rp.ctypes.data, ci.ctypes.data, va.ctypes.data
             mem = SKR_MEM_HOST
@@ -197,6 +239,7 @@ class Matrix:
         self.n = int(n)
         self.nnz = nnz
         self.dtype = dtype
+        self.version = 0          # bumped by update_values (autograd checks it)
         f = skr_format_opts(SKR_FMT_SELL if fmt == "sell" else SKR_FMT_CSR, sell_C, sell_sigma, int(make_fp32))
         h = _VP()
         _check(ctx, lib.skr_matrix_create(ctx.handle, self.n, nnz, _VP(p_rp), _VP(p_ci), _VP(p_va), dtype, mem,
@@ -210,9 +253,14 @@ class Matrix:
         return cls(ctx, csr.n, csr.indptr, csr.indices, csr.data, **kw)
 
     def update_values(self, data):
+        if len(data.shape) != 1 or int(data.shape[0]) != self.nnz:
+            raise ValueError(f"values must be a 1-D array of nnz = {self.nnz} entries")
+        if _dtype_code(data) != self.dtype:
+            raise ValueError("values must have the matrix's element type")
         _order_torch(data)
         p, mem, _, keep = _ptr_mem(data)
         _check(self.ctx, load_library().skr_matrix_update_values(self.handle, _VP(p), mem))
+        self.version += 1
 
     def ilu0(self):
         """skr_matrix_ilu0: attach right no-fill ILU factors (used by solves with
@@ -269,9 +317,10 @@ def solve(ctx: Context, A: Matrix, B, method: str, X=None, x0_zero: bool = False
     with x0_zero the contents of X are ignored (X0 = 0).  precond='ilu0':
     right ILU(0) preconditioning (A.ilu0() first).  Returns (X, SolveInfo)."""
     lib = load_library()
+    _check_block(B, A.n, A.dtype, "B")
+    if X is not None:
+        _check_block(X, A.n, A.dtype, "X", like=B)
     pB, memB, dt, keepB = _ptr_mem(B)
-    if dt != A.dtype:
-        raise ValueError("B dtype must match A's dtype")
     n, s = B.shape
     if X is None:
         zero_x0 = 1
@@ -315,6 +364,9 @@ def solve(ctx: Context, A: Matrix, B, method: str, X=None, x0_zero: bool = False
 def spmm(ctx: Context, A: Matrix, X, Y=None, adjoint: bool = False, sync: bool = True):
     """skr_spmm: Y = A X (or A^H X).  With device tensors and sync=False the
     product is only enqueued on the context's stream (the caller orders it)."""
+    _check_block(X, A.n, A.dtype, "X")
+    if Y is not None:
+        _check_block(Y, A.n, A.dtype, "Y", like=X)
     pX, mem, dt, keep = _ptr_mem(X)
     n, s = X.shape
     if Y is None:
@@ -323,7 +375,9 @@ def spmm(ctx: Context, A: Matrix, X, Y=None, adjoint: bool = False, sync: bool =
             Y = torch.empty_like(X)
         else:
             Y = np.empty_like(keep)
-    pY, _, _, _ = _ptr_mem(Y)
+    pY, memY, _, _ = _ptr_mem(Y)
+    if memY != mem:
+        raise ValueError("X and Y must live in the same memory")
     if sync:
         _order_torch(X, Y)
     _check(ctx, load_library().skr_spmm(ctx.handle, A.handle, s, _VP(pX), s, _VP(pY), s, mem, int(adjoint)))
@@ -335,6 +389,9 @@ def spmm(ctx: Context, A: Matrix, X, Y=None, adjoint: bool = False, sync: bool =
 
 def precond_apply(ctx: Context, A: Matrix, Z, Y=None, adjoint: bool = False):
     """skr_precond_apply: Y = M^-1 Z (or M^-H Z) with A's ILU(0) factors."""
+    _check_block(Z, A.n, A.dtype, "Z")
+    if Y is not None:
+        _check_block(Y, A.n, A.dtype, "Y", like=Z)
     pZ, mem, dt, keep = _ptr_mem(Z)
     n, s = Z.shape
     if Y is None:
@@ -343,7 +400,9 @@ def precond_apply(ctx: Context, A: Matrix, Z, Y=None, adjoint: bool = False):
             Y = torch.empty_like(Z)
         else:
             Y = np.empty_like(keep)
-    pY, _, _, _ = _ptr_mem(Y)
+    pY, memY, _, _ = _ptr_mem(Y)
+    if memY != mem:
+        raise ValueError("Z and Y must live in the same memory")
     _order_torch(Z, Y)
     _check(ctx, load_library().skr_precond_apply(ctx.handle, A.handle, s, _VP(pZ), s, _VP(pY), s, mem,
                                                  int(adjoint)))
@@ -352,6 +411,10 @@ def precond_apply(ctx: Context, A: Matrix, Z, Y=None, adjoint: bool = False):
 
 def sddmm(ctx: Context, A: Matrix, G, X, scale: float = -1.0, out=None):
     """skr_sddmm: out[k] = scale * sum_c G[i_k, c] conj(X[j_k, c]) on A's pattern."""
+    _check_block(G, A.n, A.dtype, "G")
+    _check_block(X, A.n, A.dtype, "X", like=G)
+    if out is not None and (len(out.shape) != 1 or int(out.shape[0]) != A.nnz or _dtype_code(out) != A.dtype):
+        raise ValueError(f"out must be a 1-D array of nnz = {A.nnz} entries of the matrix's element type")
     pG, mem, dt, kg = _ptr_mem(G)
     pX, _, _, kx = _ptr_mem(X)
     n, s = G.shape
@@ -361,7 +424,9 @@ def sddmm(ctx: Context, A: Matrix, G, X, scale: float = -1.0, out=None):
             out = torch.empty(A.nnz, dtype=G.dtype, device=G.device)
         else:
             out = np.empty(A.nnz, dtype=kg.dtype)
-    pO, _, _, _ = _ptr_mem(out)
+    pO, memO, _, _ = _ptr_mem(out)
+    if _ptr_mem(X)[1] != mem or memO != mem:
+        raise ValueError("G, X and out must live in the same memory")
     _order_torch(G, X, out)
     _check(ctx, load_library().skr_sddmm(ctx.handle, A.handle, s, _VP(pG), _VP(pX), _VP(pO), scale, mem))
     if mem == SKR_MEM_DEVICE:

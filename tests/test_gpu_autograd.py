@@ -59,9 +59,45 @@ def test_gradient_matches_dense_lu(env, precision):
     assert np.linalg.norm(gB - GBr) / np.linalg.norm(GBr) < 1e-6
 
 
+def test_two_solves_share_one_matrix(env):
+    """Two forward solves with different values on one Matrix, then one backward
+    pass through both: each solve's gradient must use its own A (the second
+    forward pass overwrote the matrix's values before the first backward)."""
+    import torch
+    P, ctx = env
+    prob = I.config(5, "small")
+    A, B, Xt = prob.A, prob.B, prob.extra["X_target"]
+    vals2 = A.data * 1.25 + 0.01 * np.random.default_rng(7).standard_normal(A.nnz) * (A.data != 0)
+    M = P.Matrix.from_csr(ctx, A)
+    v1 = torch.tensor(A.data, device="cuda", requires_grad=True)
+    v2 = torch.tensor(vals2, device="cuda", requires_grad=True)
+    Bt = torch.tensor(B, device="cuda", requires_grad=True)
+    Xtt = torch.tensor(Xt, device="cuda")
+    X1 = P.sparse_solve(v1, Bt, M, "egl_bicg", 1e-11, "fp64")
+    X2 = P.sparse_solve(v2, Bt, M, "egl_bicg", 1e-11, "fp64")
+    L = ((X1 - Xtt) ** 2).sum() + 0.5 * ((X2 - Xtt) ** 2).sum()
+    L.backward()
+    M.close()
+    rows = np.repeat(np.arange(A.n), np.diff(A.indptr))
+    gB_ref = np.zeros_like(B)
+    for vals, w, g in ((A.data, 1.0, v1.grad), (vals2, 0.5, v2.grad)):
+        Ad = A.to_scipy().toarray()
+        Ad[rows, A.indices] = vals
+        Xd = np.linalg.solve(Ad, B)
+        _, GBr, GAr = O.dense_solve_grad(Ad, B, 2 * w * (Xd - Xt))
+        gv_ref = GAr[rows, A.indices]
+        err = np.linalg.norm(g.cpu().numpy() - gv_ref) / np.linalg.norm(gv_ref)
+        say("two solves, one matrix: grad_vals rel err", err)
+        assert err < 1e-6
+        gB_ref += GBr
+    assert np.linalg.norm(Bt.grad.cpu().numpy() - gB_ref) / np.linalg.norm(gB_ref) < 1e-6
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
 @pytest.mark.parametrize("grid", [64, 1024])
-def test_gradient_matches_finite_differences(env, grid):
-    """Central differences of L with solves at 1e-12.  Along F (on B) central
+def test_gradient_matches_finite_differences(env, grid, precision):
+    """Central differences of L with solves at 1e-12 (with FP32 inner solves,
+    1e-12 is the outer FP64 refinement's target).  Along F (on B) central
     differences are exact, since L is quadratic in B.  Along E (on A's stored
     values) the step is swept over relative sizes 1e-7..1e-10 (kappa(A) grows
     like the grid size squared, so a larger step leaves the linear regime);
@@ -74,14 +110,14 @@ def test_gradient_matches_finite_differences(env, grid):
     rng = np.random.default_rng(3)
     E = rng.standard_normal(A.nnz)
     F = rng.standard_normal(B.shape)
-    L0, gv, gB, _ = _loss_and_grads(P, ctx, A, B, Xt, "egl_bicg", "fp64", 1e-12)
+    L0, gv, gB, _ = _loss_and_grads(P, ctx, A, B, Xt, "egl_bicg", precision, 1e-12)
     M = P.Matrix.from_csr(ctx, A)
     Xtt = torch.tensor(Xt, device="cuda")
 
     def loss(hE, hF):
         vals = torch.tensor(A.data + hE * E, device="cuda")
         Bt = torch.tensor(B + hF * F, device="cuda")
-        X = P.sparse_solve(vals, Bt, M, "egl_bicg", 1e-12, "fp64")
+        X = P.sparse_solve(vals, Bt, M, "egl_bicg", 1e-12, precision)
         return float(((X - Xtt) ** 2).sum())
 
     hF = 1e-3 * np.linalg.norm(B) / np.linalg.norm(F)
@@ -95,7 +131,7 @@ def test_gradient_matches_finite_differences(env, grid):
         fdE = (loss(hE, 0.0) - loss(-hE, 0.0)) / (2 * hE)
         relE.append(abs(fdE - anE) / abs(anE))
     M.close()
-    say(f"grid {grid}: F direction rel {relF:.2e}; E direction rel over steps 1e-7..1e-10: "
+    say(f"grid {grid} {precision}: F direction rel {relF:.2e}; E direction rel over steps 1e-7..1e-10: "
         + ", ".join(f"{x:.1e}" for x in relE))
     assert relF <= 1e-6
     assert min(relE) <= 1e-6
