@@ -2,9 +2,8 @@
 //
 // CSR: a group of L lanes owns one row; each lane owns columns lane + L*j
 // (j < J) of the block, so every stored nonzero a_ij is read once for all s
-// right-hand sides and the s values X[j, :] are one contiguous read
-// (Section 1: "reading and storing A only once while updating the iterates for
-// all s r.h.s. simultaneously").
+// right-hand sides and the s values X[j, :] are one contiguous read: the
+// memory-traffic saving that motivates the simultaneous methods (Section 1).
 //
 // SELL-C-sigma: rows are sorted by length inside windows of sigma rows and cut
 // into chunks of C rows; a chunk stores its entries column-major (slot k of all
@@ -285,11 +284,15 @@ __global__ __launch_bounds__(kBlock) void k_spmm_csr(const Ctl* ctl, CsrOp<T> A,
 }
 
 // Real blocks with even s <= 16: 8 lanes per row, lane l holding columns 2l and
-// 2l + 1 (one 16-byte load of X per nonzero for FP64).  A DPP row of 16 lanes
+// 2l + 1 (one 16-byte load of X per nonzero for FP64).  A group of 16 lanes
 // carries two matrix rows; the entries of both are loaded 8 at a time (lane u
-// of each half loads entry u) and broadcast inside their half.  A wave owns 16
-// consecutive rows per pass (two passes of 8); products are accumulated in FP64
-// also for FP32 data.  The matrix stream (indices,
+// of each half loads entry u) and staged in LDS, from where the 8 lanes of the
+// row read each entry back (one address per half: an LDS broadcast).  The
+// column indices are read back before the X gathers are issued and each value
+// just before its FMA, so no lane holds the 8 broadcast entries in registers
+// while the gathers are in flight; that keeps the FP64 kernel at 3 waves per
+// SIMD.  A wave owns 16 consecutive rows per pass (two groups of 8); products
+// are accumulated in FP64 also for FP32 data.  The matrix stream (indices,
 // values) is read and Y is written with non-temporal hints, so that L2 keeps
 // the X rows that neighbouring matrix rows gather again.  Epilogues see the
 // tile-16 layout: the wave's 16 x 16 result tile goes through LDS and each
@@ -322,6 +325,8 @@ __global__ __launch_bounds__(kBlock) void k_spmm_csr8(const Ctl* ctl, CsrOp<T> A
     const bool colok = 2 * l8 < s;          // s is even: both of the lane's columns exist, or neither
     const int cofs = colok ? 2 * l8 : 0;
     __shared__ T tiles[TILE ? kWaves : 1][TILE ? 16 * 17 : 1];
+    __shared__ __align__(16) int ecol[kWaves][16][U];   // staged entries: [wave][row of the pass][slot]
+    __shared__ __align__(16) T eval[kWaves][16][U];
     typename Epi::St st;
     epi.init(st);
     const int tc = threadIdx.x & 15, tq = (threadIdx.x >> 4) & 3;   // tile-16 layout of the epilogue
@@ -397,23 +402,42 @@ __global__ __launch_bounds__(kBlock) void k_spmm_csr8(const Ctl* ctl, CsrOp<T> A
 #pragma unroll
             for (int p = 0; p < 2; ++p) more |= k0[p] + off + U < k1[p];
             more = __any(more);
+            // stage this round's entries: row 8p + 2g + half of the wave, slot l8
 #pragma unroll
             for (int p = 0; p < 2; ++p) {
-                sfor<0, U>([&](auto ic) {
-                    constexpr int u = decltype(ic)::value;
-                    const int c0 = rbc32<u>(mc[p]), c1 = rbc32<u + 8>(mc[p]);
-                    const T a0 = rbc64<u>(ma[p]), a1 = rbc64<u + 8>(ma[p]);
-                    const int c = half ? c1 : c0;
-                    const T a = half ? a1 : a0;
-                    const P2 xv = *reinterpret_cast<const P2*>(X + (size_t)c * s + cofs);
-                    ax[p] = fma((double)a, (double)xv.x, ax[p]);
-                    ay[p] = fma((double)a, (double)xv.y, ay[p]);
-                });
+                ecol[w][8 * p + 2 * g + half][l8] = mc[p];
+                eval[w][8 * p + 2 * g + half][l8] = ma[p];
+            }
+            __builtin_amdgcn_wave_barrier();
+            int cc[2][U];
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                const int4* cr = reinterpret_cast<const int4*>(&ecol[w][8 * p + 2 * g + half][0]);
+                const int4 c03 = cr[0], c47 = cr[1];
+                cc[p][0] = c03.x; cc[p][1] = c03.y; cc[p][2] = c03.z; cc[p][3] = c03.w;
+                cc[p][4] = c47.x; cc[p][5] = c47.y; cc[p][6] = c47.z; cc[p][7] = c47.w;
+            }
+            P2 xv[2][U];
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+#pragma unroll
+                for (int u = 0; u < U; ++u) xv[p][u] = *reinterpret_cast<const P2*>(X + (size_t)cc[p][u] * s + cofs);
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                const T* er = &eval[w][8 * p + 2 * g + half][0];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const T a = er[u];
+                    ax[p] = fma((double)a, (double)xv[p][u].x, ax[p]);
+                    ay[p] = fma((double)a, (double)xv[p][u].y, ay[p]);
+                }
             }
             if (off == 0) entries(nk0, nk1, 0, nmc, nma);   // next step's first entries
             if (!more) break;
+            __builtin_amdgcn_wave_barrier();                 // every read of this round precedes the next writes
             entries(k0, k1, off + U, mc, ma);                // rows longer than U: the rest in place
         }
+        __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
             if (valid[p] && colok) {

@@ -10,7 +10,11 @@ launches and checks, for ragged sizes, that
     in-place reads of longer rows) is inside ci/va, which hold max(nnz, 1)
     entries;
   - every epilogue operand read (tile layout for the Grams, the lane's own rows
-    and columns for the row sums) is inside the n x s block.
+    and columns for the row sums) is inside the n x s block;
+  - the LDS staging of a round's entries: each lane of a wave writes one slot
+    of the wave's [16 rows][8 slots] area, every slot is written exactly once,
+    and the 8 slots a lane reads back for its row are the ones the 8 lanes of
+    that row wrote.
 
 The model restates the kernel's index arithmetic; a change to one side must be
 made on the other.
@@ -100,6 +104,32 @@ def walk_csr8(n, rp, s, nb):
             i, valid, k0, k1 = ni, nvalid, nk0, nk1
             base += step
     return written
+
+
+def test_csr8_lds_staging_layout():
+    t = np.arange(BLOCK)
+    lane = t & 15
+    half = lane >> 3
+    l8 = lane & 7
+    w = t >> 6
+    g = (t >> 4) & 3
+    waves = BLOCK // 64
+    owner = -np.ones((waves, 16, U), dtype=np.int64)
+    for p in range(2):
+        lr = 8 * p + 2 * g + half
+        assert np.all((lr >= 0) & (lr < 16))
+        for th in range(BLOCK):
+            assert owner[w[th], lr[th], l8[th]] == -1          # written once
+            owner[w[th], lr[th], l8[th]] = th
+    assert np.all(owner >= 0)                                  # every slot written
+    for p in range(2):
+        lr = 8 * p + 2 * g + half
+        for th in range(BLOCK):
+            writers = owner[w[th], lr[th], :]
+            # the writers of the row a lane reads are the 8 lanes of its own row
+            # group (same wave, same 16-lane group, same half), slot u by lane u
+            assert np.all(w[writers] == w[th]) and np.all(g[writers] == g[th]) and np.all(half[writers] == half[th])
+            assert np.array_equal(l8[writers], np.arange(U))
 
 
 def _ragged_rp(n, seed):
