@@ -2,6 +2,7 @@
 benchmark uses: sampled outputs the oracle computes row by row, iterates after
 a few iterations against the oracle, and properties that hold at any size
 (true residual recomputed on the CPU)."""
+import os
 import sys
 
 import numpy as np
@@ -77,6 +78,76 @@ def test_first_iterations_full_convdiff3d(env, cfg2, method):
     say(f"  err {err:.2e}")
     assert info.iterations == 3 and err < 1e-10
     np.testing.assert_allclose(info.history, ref.history, rtol=1e-10)
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _golden_counts(grid=128):
+    """{method: {seed: iterations}} of converged oracle runs on the benchmark
+    workload (tests/golden/make_fullsize_counts.py)."""
+    out = {}
+    for line in open(os.path.join(GOLDEN, "fullsize_iterations.txt")):
+        f = line.split()
+        if f and not f[0].startswith("#") and int(f[0]) == grid and int(f[3]) == 0:
+            out.setdefault(f[1], {})[int(f[2])] = int(f[4])
+    return out
+
+
+@pytest.mark.parametrize("method", ["bl_bicg_rq", "egl_qmr", "bl_bicgstab_rq"])
+def test_fullsize_iteration_count(env, cfg2, method):
+    """The benchmark's own solves, in its launch configuration (tol 1e-8, at
+    most 1200 iterations): the GPU's iteration count within 5% of the oracle's
+    count on the same inputs, plus the spread of the oracle's own counts over
+    runs with B perturbed by 1e-15 (where they are on file)."""
+    P, ctx = env
+    import torch
+    counts = _golden_counts().get(method, {})
+    assert 0 in counts, f"no oracle count on file for {method}"
+    ref = counts[0]
+    spread = max(counts.values()) - min(counts.values())
+    A = P.Matrix.from_csr(ctx, cfg2.A)
+    X, info = P.solve(ctx, A, torch.from_numpy(cfg2.B).cuda(), method, tol=1e-8, maxit=1200)
+    A.close()
+    say(f"full 128^3 {method}: gpu it={info.iterations} status={info.status_name} | oracle it={ref} "
+        f"(perturbed-oracle counts {sorted(counts.values())}, spread {spread})")
+    assert info.status == 0
+    assert abs(info.iterations - ref) <= max(1, int(0.05 * ref)) + spread
+
+
+def _xstar_rows():
+    rows, vals = [], []
+    for line in open(os.path.join(GOLDEN, "fullsize_xstar_rows.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        f = line.split()
+        rows.append(int(f[0]))
+        vals.append([float(v) for v in f[1:]])
+    return np.array(rows), np.array(vals)
+
+
+def test_mixed_full_convdiff3d_against_xstar(env, cfg2):
+    """FP32 inner solves inside FP64 refinement on the full benchmark workload:
+    at the timing tolerance 1e-8 the true residual (recomputed on the CPU) is
+    met; the parity run tightens the outer tolerance to 1e-12 and its X agrees
+    with the oracle's X* (eGl-QMR to 1e-12) to 1e-8 on the sampled rows."""
+    P, ctx = env
+    import torch
+    rows, xs = _xstar_rows()
+    A = P.Matrix.from_csr(ctx, cfg2.A)
+    Bd = torch.from_numpy(cfg2.B).cuda()
+    S = cfg2.A.to_scipy()
+    for tol in (1e-8, 1e-12):
+        X, info = P.solve(ctx, A, Bd, "egl_qmr", tol=tol, precision="fp32_refine", max_outer=20)
+        X = X.cpu().numpy()
+        rel = np.linalg.norm(cfg2.B - S @ X) / np.linalg.norm(cfg2.B)
+        err = np.linalg.norm(X[rows] - xs) / np.linalg.norm(xs)
+        say(f"  mixed egl_qmr tol={tol:g}: status={info.status_name} outer={info.outer_iterations} "
+            f"inner it={info.iterations} true_res_cpu={rel:.2e} err_vs_X*(sampled rows)={err:.2e}")
+        assert info.status == 0 and rel <= 1.5 * tol
+        if tol <= 1e-12:
+            assert err <= 1e-8, err
+    A.close()
 
 
 @pytest.mark.parametrize("method,precision", [("egl_qmr", "fp64"), ("bl_bicgstab_rq", "fp64"),
