@@ -13,7 +13,8 @@ solve's own wall time, which overlaps the others'.
 Also reported: the roofline position of the sparse x block product (the kernel
 every iteration runs; algorithmic bytes A_b + 2 n s 8 per launch, timed with HIP
 events on the stream it runs on) and the CPU oracle's throughput on a bounded
-sample (a few iterations per method, scaled by the GPU's iteration counts).
+sample (set-up plus 20 timed iterations over the three methods, scaled by the
+oracle's own converged iteration counts).
 """
 from __future__ import annotations
 
@@ -87,30 +88,85 @@ def spmm_roofline(pkg, ctx, A, n, nnz, s, stream, reps=50):
             "kernel": kernel, "avg_us": round(ms * 1e3, 2), "bytes_per_launch": bytes_alg}
 
 
-def cpu_baseline(prob, gpu_iters, solved, iters_per_method=2):
-    """The oracle, untuned, on a bounded sample: `iters_per_method` iterations of
-    each method on the full problem, scaled to a full solve with the GPU's
-    iteration counts; the same number of solved right-hand sides as the GPU
-    step counts in the numerator."""
+# iterations timed per method by the CPU baseline (20 in all), beyond one
+# untimed-per-iteration run that captures the set-up
+CPU_SAMPLE_ITERS = {"bl_bicg_rq": 4, "egl_qmr": 10, "bl_bicgstab_rq": 6}
+
+
+def oracle_counts(grid, path=None):
+    """The oracle's own converged iteration counts on the unperturbed workload
+    (seed 0), from the file the oracle-only script tests/golden/
+    make_fullsize_counts.py writes; {} when the grid has no entry."""
+    path = path or os.path.join(ROOT, "tests", "golden", "fullsize_iterations.txt")
+    out = {}
+    try:
+        for line in open(path):
+            f = line.split()
+            if not f or f[0].startswith("#") or len(f) < 6:
+                continue
+            if int(f[0]) == grid and int(f[2]) == 0 and int(f[3]) == 0:
+                out[f[1]] = int(f[4])
+    except OSError:
+        pass
+    return out
+
+
+def host_cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(prob, gpu_iters, solved, grid, sample_iters=None):
+    """The oracle, untuned, on a bounded sample of the workload: per method one
+    run of 1 iteration and one of 1 + k iterations on the full problem.  Their
+    difference gives the time per iteration without the set-up (QR of the
+    right-hand sides, shadow initialisation, final residual), the first run the
+    set-up; a full solve is set-up + per-iteration time x the oracle's own
+    converged iteration count (the GPU's count is used only where the oracle's
+    is not on file, and the sample then says so).  The numerator is the same
+    number of solved right-hand sides as the GPU step's."""
     import oracle
+    sample_iters = sample_iters or CPU_SAMPLE_ITERS
     try:
         from threadpoolctl import threadpool_info
         cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
     except Exception:
         cores = os.cpu_count() or 1
-    s = prob.B.shape[1]
+    counts = oracle_counts(grid)
     total = 0.0
+    used = {}
     for m in METHODS:
+        k = sample_iters[m]
         t = time.perf_counter()
-        oracle.solve(prob.A, prob.B, m, tol=0.0, maxit=iters_per_method)
-        dt = time.perf_counter() - t
-        total += dt / iters_per_method * gpu_iters[m]
-        log(f"cpu oracle {m}: {iters_per_method} iterations in {dt:.1f} s")
+        oracle.solve(prob.A, prob.B, m, tol=0.0, maxit=1)
+        t1 = time.perf_counter() - t
+        t = time.perf_counter()
+        oracle.solve(prob.A, prob.B, m, tol=0.0, maxit=1 + k)
+        tk = time.perf_counter() - t
+        per_it = max(tk - t1, 0.0) / k
+        setup = max(t1 - per_it, 0.0)
+        count = counts.get(m)
+        used[m] = {"oracle_iterations": count if count is not None else None,
+                   "scaled_by": count if count is not None else gpu_iters[m],
+                   "s_per_iteration": round(per_it, 3), "setup_s": round(setup, 3)}
+        total += setup + per_it * used[m]["scaled_by"]
+        log(f"cpu oracle {m}: set-up {setup:.2f} s, {per_it:.2f} s per iteration ({k} timed), "
+            f"x {used[m]['scaled_by']} iterations")
     value = solved / total
+    src = "the oracle's own converged counts" if all(u["oracle_iterations"] for u in used.values()) else \
+        "the oracle's counts where on file, else the GPU's"
     return {"value": round(value, 6), "unit": "RHS/s", "cores": cores, "kind": "oracle",
-            "sample": f"{iters_per_method} iterations of each method on the full 128^3 problem, "
-                      f"scaled by the GPU iteration counts {gpu_iters}; numpy/scipy FP64 "
-                      f"(BLAS threads={cores}, scipy sparse products single-threaded)"}
+            "cpu_model": host_cpu_model(), "per_method": used,
+            "sample": f"1 and 1+k iterations of each method on the full {grid}^3 problem "
+                      f"(k = {dict(sample_iters)}, {sum(sample_iters.values())} timed iterations in all); "
+                      f"set-up + per-iteration time x {src}; numpy/scipy FP64, BLAS threads={cores}, "
+                      f"scipy sparse products single-threaded"}
 
 
 # Table 2 of the paper (no preconditioning; Matlab on a CPU, its own
@@ -210,6 +266,98 @@ def config_solves(pkg, ctx, inputs, k, methods, precision, fmt, reps):
     return rows
 
 
+def config1_latency(pkg, inputs, reps=7):
+    """The small 2D workload (32 x 32 grid, n = 1024, s = 4, FP64): Gl-BiCG and
+    eGl-BiCG to 1e-8 with the iteration captured in a hipGraph and launched
+    eagerly; the median solve time of `reps`, microseconds per iteration, and
+    the oracle's full solve in seconds (untuned, on the host)."""
+    import numpy as np
+    import torch
+    import oracle
+    prob = inputs.config(1)
+    ctx = pkg.Context(0)
+    A = pkg.Matrix.from_csr(ctx, prob.A)
+    B = torch.from_numpy(prob.B).cuda()
+    X = torch.zeros_like(B)
+    rows = {}
+    for m in ("gl_bicg", "egl_bicg"):
+        r = {}
+        for graph in (True, False):
+            ts = []
+            for _ in range(reps + 1):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                _, info = pkg.solve(ctx, A, B, m, X=X, x0_zero=True, tol=1e-8, use_graph=graph)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t)
+            med = float(np.median(ts[1:]))      # the first solve also builds the graph
+            r["graph" if graph else "eager"] = {"ms_per_solve": round(med * 1e3, 3),
+                                                "us_per_iteration": round(med * 1e6 / info.iterations, 2),
+                                                "iterations": info.iterations, "status": info.status_name}
+        t = time.perf_counter()
+        ref = oracle.solve(prob.A, prob.B, m, tol=1e-8)
+        r["oracle"] = {"s_per_solve": round(time.perf_counter() - t, 4), "iterations": ref.iterations}
+        rows[m] = r
+        log(f"config 1 {m}: graph {r['graph']['us_per_iteration']} us/it, eager {r['eager']['us_per_iteration']} "
+            f"us/it, oracle {r['oracle']['s_per_solve']} s")
+    A.close()
+    ctx.close()
+    return {"workload": prob.name, "n": prob.A.n, "s": int(prob.B.shape[1]), "tol": 1e-8, "methods": rows}
+
+
+def accel_ratio(pkg, inputs, configs=(2, 3, 4, 5), reps=20):
+    """Table 1's blocking gain a, measured as the paper does: the time of s
+    products with single vectors over the time of one product with the n x s
+    block (same matrix, CSR, FP64 or complex FP64), with HIP events on the
+    context's stream; both products with A and with A^H."""
+    import numpy as np
+    import torch
+    stream = torch.cuda.Stream()
+    ctx = pkg.Context(0, stream=stream.cuda_stream)
+    out = []
+    for k in configs:
+        prob = inputs.config(k, "full")
+        A = pkg.Matrix.from_csr(ctx, prob.A)
+        Bk = np.ascontiguousarray(prob.B)
+        s = Bk.shape[1]
+        X = torch.from_numpy(Bk).cuda()
+        Y = torch.empty_like(X)
+        cols = [torch.from_numpy(np.ascontiguousarray(Bk[:, j:j + 1])).cuda() for j in range(s)]
+        ycols = [torch.empty_like(c) for c in cols]
+        torch.cuda.synchronize()
+        row = {"workload": prob.name, "n": prob.A.n, "nnz": prob.A.nnz, "s": s}
+        for adj in (False, True):
+            def timed(fn):
+                with torch.cuda.stream(stream):
+                    for _ in range(3):
+                        fn()
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    for _ in range(reps):
+                        fn()
+                    e1.record(stream)
+                e1.synchronize()
+                return e0.elapsed_time(e1) * 1e3 / reps
+
+            t_blk = timed(lambda: pkg.spmm(ctx, A, X, Y, adjoint=adj, sync=False))
+
+            def singles():
+                for c, y in zip(cols, ycols):
+                    pkg.spmm(ctx, A, c, y, adjoint=adj, sync=False)
+            t_vec = timed(singles)
+            key = "AH" if adj else "A"
+            row[key] = {"spmm_us": round(t_blk, 1), "s_spmv_us": round(t_vec, 1), "a": round(t_vec / t_blk, 2)}
+            log(f"{prob.name} {key}: one block product {t_blk:.1f} us, {s} vector products {t_vec:.1f} us, "
+                f"a = {t_vec / t_blk:.2f}")
+        out.append(row)
+        A.close()
+        del X, Y, cols, ycols
+        torch.cuda.empty_cache()
+    ctx.close()
+    return out
+
+
 def sell_sweep(pkg, ctx, inputs, stream, reps=20):
     """Sparse x block product on the power-law workload (complex, s = 32, 2^20
     rows with lengths 4..400): CSR, and SELL-C-sigma for C in {16, 32, 64} and
@@ -259,7 +407,6 @@ def main():
     ap.add_argument("--grid", type=int, default=128)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=2)
     ap.add_argument("--mixed-steps", type=int, default=1)
     ap.add_argument("--maxit", type=int, default=1200,
                     help="iteration cap per solve: the paper's largest cap (Section 5.2); the "
@@ -284,6 +431,10 @@ def main():
                          "--methods (default: the workload's own list)")
     ap.add_argument("--precision", default="fp64", help="with --config: fp64 or fp32_refine")
     ap.add_argument("--format", default="csr", help="with --config: csr or sell")
+    ap.add_argument("--accel-ratio", action="store_true",
+                    help="instead of the benchmark: Table 1's blocking gain a (s vector products over one "
+                         "block product) on workloads 2-5 at full size")
+    ap.add_argument("--no-config1", action="store_true", help="skip the small-workload latency figures")
     ap.add_argument("--sell-sweep", action="store_true",
                     help="instead of the benchmark: the sparse x block product on the power-law workload "
                          "in CSR and SELL-C-sigma (C in 16, 32, 64; sigma in C, 256, 1024, 8192)")
@@ -305,6 +456,10 @@ def main():
                              args.precision, args.format, args.reps)
         print(json.dumps({"config_solves": rows}), flush=True)
         ctx.close()
+        return
+
+    if args.accel_ratio:
+        print(json.dumps({"accel_ratio": accel_ratio(pkg, inputs)}), flush=True)
         return
 
     if args.sell_sweep:
@@ -355,28 +510,31 @@ def main():
             c_m = pkg.Context(0, stream=st_m.cuda_stream)
             lanes[m] = (c_m, pkg.Matrix.from_csr(c_m, A_csr), st_m)
 
-    def solve_one(m, per_method):
+    mixed_kw = dict(precision="fp32_refine", inner_tol=1e-4, max_outer=20)
+
+    def solve_one(m, per_method, mixed, out):
         c_m, A_m = (lanes[m][0], lanes[m][1]) if lanes else (ctx, A)
         tm = time.perf_counter()
-        X, info = pkg.solve(c_m, A_m, B, m, X=Xs[m], x0_zero=True, tol=args.tol, maxit=args.maxit)
+        X, info = pkg.solve(c_m, A_m, B, m, X=Xs[m], x0_zero=True, tol=args.tol, maxit=args.maxit,
+                            **(mixed_kw if mixed else {}))
         if per_method is not None:
             if lanes:
                 lanes[m][2].synchronize()
             else:
                 torch.cuda.synchronize()
             per_method[m] += time.perf_counter() - tm
-        infos[m] = (X, info)
+        out[m] = (X, info)
 
-    def solve_all(per_method=None):
+    def solve_all(per_method=None, mixed=False, out=infos):
         if not lanes:
             for m in METHODS:
-                solve_one(m, per_method)
+                solve_one(m, per_method, mixed, out)
             return
         errors = {}
 
         def run(m):
             try:
-                solve_one(m, per_method)
+                solve_one(m, per_method, mixed, out)
             except Exception as ex:   # re-raised below, after every thread has ended
                 errors[m] = ex
 
@@ -410,22 +568,27 @@ def main():
     solved = sum(s for m in METHODS if infos[m][1].status == 0)
     value = solved / (total / args.steps)
 
-    # the same step with FP32 inner solves inside FP64 iterative refinement
+    # the same step with FP32 inner solves inside FP64 iterative refinement, in
+    # the same execution mode as the FP64 step (concurrent or one after another)
     mixed = {}
     t_mixed = 0.0
     if args.mixed_steps > 0:
+        minfo = {}
+        mper = {m: 0.0 for m in METHODS}
+        solve_all(mixed=True, out=minfo)          # warm-up: FP32 value copies, graphs
+        torch.cuda.synchronize()
+        tm0 = time.perf_counter()
         for k in range(args.mixed_steps):
-            for m in METHODS:
-                tm = time.perf_counter()
-                X, info = pkg.solve(ctx, A, B, m, X=Xs[m], x0_zero=True, tol=args.tol, maxit=args.maxit,
-                                    precision="fp32_refine", inner_tol=1e-4, max_outer=20)
-                torch.cuda.synchronize()
-                dt = time.perf_counter() - tm
-                t_mixed += dt
-                mixed[m] = {"status": info.status_name, "outer": info.outer_iterations,
-                            "outer_redone_in_fp64": info.fp64_outer_iterations,
-                            "inner_iterations": info.iterations, "rel_res_true": info.rel_res_true,
-                            "s_per_solve": round(dt, 4), "rhs_per_s": round(s / dt, 3)}
+            solve_all(mper, mixed=True, out=minfo)
+            torch.cuda.synchronize()
+        t_mixed = time.perf_counter() - tm0
+        for m in METHODS:
+            info = minfo[m][1]
+            dt = mper[m] / args.mixed_steps
+            mixed[m] = {"status": info.status_name, "outer": info.outer_iterations,
+                        "outer_redone_in_fp64": info.fp64_outer_iterations,
+                        "inner_iterations": info.iterations, "rel_res_true": info.rel_res_true,
+                        "s_per_solve": round(dt, 4), "rhs_per_s": round(s / dt, 3)}
         log("mixed step: " + ", ".join(f"{m} {mixed[m]['status']} outer={mixed[m]['outer']}" for m in METHODS))
 
     roof = spmm_roofline(pkg, ctx, A, n, nnz, s, stream)
@@ -448,10 +611,13 @@ def main():
     if args.mixed_steps > 0:
         ok = sum(s for m in METHODS if mixed[m]["status"] == "ok")
         out["mixed_fp32_refine"] = {"value": round(ok / (t_mixed / args.mixed_steps), 4), "unit": "RHS/s",
+                                    "steps": args.mixed_steps, "concurrent_solves": bool(args.concurrent),
                                     "per_method": mixed}
+    if not args.no_config1:
+        out["config1_latency"] = config1_latency(pkg, inputs)
     if not args.no_cpu:
         prob = inputs.Problem("convdiff3d", A_csr, B_np, METHODS, {})
-        out["cpu_baseline"] = cpu_baseline(prob, gpu_iters, solved, args.cpu_iters)
+        out["cpu_baseline"] = cpu_baseline(prob, gpu_iters, solved, args.grid)
     print(json.dumps(out), flush=True)
     for c_m, A_m, _ in lanes.values():
         A_m.close()
