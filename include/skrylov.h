@@ -209,6 +209,23 @@ int skr_sddmm(skr_context* ctx, const skr_matrix* A, int32_t s, const void* G, c
 int skr_block_qr(skr_context* ctx, int64_t n, int32_t s, int32_t dtype, const void* Z, void* Q,
                  double* C, int32_t mem);
 
+/* skr_block_qr without any device-memory allocation, for callers that cannot
+ * allocate device memory: tight serving loops and harnesses that forbid
+ * allocation (it synchronises the context's stream to return C, so it is not
+ * for use under stream capture).  The same thin QR, Z = Q C, by the same
+ * kernels as skr_block_qr (results identical to it), with its control block,
+ * coefficient slots and reduction partials in a static device array of the
+ * library (9 MiB per device, held until the process ends) instead of
+ * library-allocated memory.  Z and Q: device memory, n x s row-major with
+ * leading dimension s (Q may equal Z); C: s x s row-major host array (complex
+ * values interleaved).  Limits: 1 <= s <= 16 and s <= n <= 2^31 - 2^20; larger
+ * s gives SKR_E_INVALID (use skr_block_qr).  Every call on one device shares
+ * that array and leaves its contents behind, so calls that overlap on one
+ * device (two host threads or two streams) race: serialise them.  The caller
+ * allocates Q.  Returns SKR_BREAKDOWN like skr_block_qr. */
+int skr_block_qr_noalloc(skr_context* ctx, int64_t n, int32_t s, int32_t dtype, const void* Z, void* Q,
+                         double* C);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,6 +8,7 @@ arithmetic runs in the HIP library ``libskrylov.so`` behind the C ABI of
 """
 from ._binding import (  # noqa: F401
     LIB_PATH, METHODS, PRECISIONS, PRECONDS, STATUS_NAMES, Context, Matrix, SkrError, SolveInfo, block_qr,
+    block_qr_noalloc,
     load_library, opts_default, precond_apply, sddmm, solve, spmm,
 )
 

@@ -72,6 +72,8 @@ _SIGS = {
                                          ctypes.c_int32, ctypes.c_int32]),
     "skr_block_qr": (ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _VP, _VP,
                                     ctypes.POINTER(ctypes.c_double), ctypes.c_int32]),
+    "skr_block_qr_noalloc": (ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _VP, _VP,
+                                            ctypes.POINTER(ctypes.c_double)]),
 }
 
 _lib = None
@@ -452,3 +454,23 @@ def block_qr(ctx: Context, Z):
     _check(ctx, rc)
     Cm = C.view(np.complex128).reshape(s, s) if dt == SKR_C64 else C.reshape(s, s)
     return Q, Cm, rc
+
+
+def block_qr_noalloc(ctx: Context, Z, Q):
+    """skr_block_qr_noalloc: Z = Q C with no device allocation in the library.
+    Z and Q: contiguous n x s float64 / complex128 CUDA tensors (s <= 16; Q
+    may be Z).  Returns (C, status)."""
+    if not (_is_torch(Z) and Z.is_cuda and _is_torch(Q) and Q.is_cuda):
+        raise ValueError("Z and Q must be CUDA tensors")
+    if len(Z.shape) != 2 or tuple(Q.shape) != tuple(Z.shape) or _dtype_code(Q) != _dtype_code(Z):
+        raise ValueError("Q must have Z's shape and element type")
+    pZ, _, dt, _ = _ptr_mem(Z)
+    pQ, _, _, _ = _ptr_mem(Q)
+    n, s = Z.shape
+    _order_torch(Z, Q)
+    C = np.zeros(s * s * (2 if dt == SKR_C64 else 1), dtype=np.float64)
+    rc = load_library().skr_block_qr_noalloc(ctx.handle, n, s, dt, _VP(pZ), _VP(pQ),
+                                             C.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    _check(ctx, rc)
+    Cm = C.view(np.complex128).reshape(s, s) if dt == SKR_C64 else C.reshape(s, s)
+    return Cm, rc

@@ -13,6 +13,7 @@
 #include <cstdint>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -162,6 +163,8 @@ struct skr_context {
     Ctl* hin = nullptr;   // pinned
     Ctl* hout = nullptr;  // pinned
     c64* hsum = nullptr;  // pinned, small
+    c64* hmat = nullptr;  // pinned, kMaxS x kMaxS: s x s results of the allocation-free calls
+    char* scratch = nullptr;   // device address of this device's static scratch array (or null)
     std::vector<GraphEntry> graphs;
     std::vector<skr_matrix*> mats;   // live matrices (orphaned when the context goes first)
     void* stage = nullptr;           // cached staging blocks for B and X (grow-only)
@@ -195,7 +198,42 @@ struct skr_matrix {
     Ilu* ilu = nullptr;   // right ILU(0) factors (skr_matrix_ilu0), dropped when the values change
 };
 
+// ---------------------------------------------------------------- static scratch
+// Device memory of the allocation-free entry point (skr_block_qr_noalloc): its
+// control block, coefficient slots and reduction partials, at most
+// kNoAllocBytes.  Each device holds one copy for the life of the process, and
+// every call on that device shares it.  Host code never uses this name as an
+// address: the per-device address comes from hipGetSymbolAddress at context
+// creation (scratch_addr below).
+constexpr size_t kNoAllocBytes = 9u << 20;
+constexpr int kNoAllocMaxS = 16;
+__device__ __align__(256) char scratch[kNoAllocBytes];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+
+// Address of `scratch` on `device` (which must be current), looked up once per
+// device; null if the lookup failed.
+char* scratch_addr(int device, std::string* why) {
+    static std::mutex mu;
+    static char* addr[kMaxDevices] = {};
+    static bool tried[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) {
+        *why = "device index beyond the scratch table";
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    if (!tried[device]) {
+        tried[device] = true;
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e == hipSuccess) addr[device] = (char*)p;
+        else *why = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+    }
+    if (!addr[device] && why->empty()) *why = "the scratch array of this device could not be located";
+    return addr[device];
+}
 
 size_t elt(int dtype, bool fp32) {
     if (dtype == SKR_C64) return fp32 ? 8 : 16;
@@ -864,10 +902,21 @@ int skr_context_create(int device, void* hip_stream, skr_context** out) {
     if (hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess ||
         hipHostMalloc((void**)&c->hin, sizeof(Ctl), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&c->hout, sizeof(Ctl), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&c->hsum, 4 * sizeof(c64), hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void**)&c->hsum, 4 * sizeof(c64), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&c->hmat, sizeof(c64) * kMaxS * kMaxS, hipHostMallocDefault) != hipSuccess) {
+        if (c->hin) (void)hipHostFree(c->hin);
+        if (c->hout) (void)hipHostFree(c->hout);
+        if (c->hsum) (void)hipHostFree(c->hsum);
+        if (c->hmat) (void)hipHostFree(c->hmat);
+        if (c->own) (void)hipStreamDestroy(c->own);
         delete c;
         return SKR_E_HIP;
     }
+    // the allocation-free entry point's scratch on this device (once per device;
+    // a failed lookup only disables that entry point, which then reports it)
+    std::string why;
+    c->scratch = scratch_addr(device, &why);
+    if (!c->scratch) c->err = why;
     *out = c;
     return SKR_OK;
 }
@@ -883,6 +932,7 @@ int skr_context_destroy(skr_context* c) {
     if (c->hin) (void)hipHostFree(c->hin);
     if (c->hout) (void)hipHostFree(c->hout);
     if (c->hsum) (void)hipHostFree(c->hsum);
+    if (c->hmat) (void)hipHostFree(c->hmat);
     if (c->own) (void)hipStreamDestroy(c->own);
     delete c;
     return SKR_OK;
@@ -1302,6 +1352,57 @@ int skr_block_qr(skr_context* c, int64_t n64, int32_t s, int32_t dtype, const vo
                     Cout[2 * k + 1] = Cm[k].y;
                 } else {
                     Cout[k] = Cm[k].x;
+                }
+            }
+            return ok ? SKR_OK : SKR_BREAKDOWN;
+        };
+        return dtype == SKR_C64 ? run(c64{}) : run(double{});
+    });
+}
+
+int skr_block_qr_noalloc(skr_context* c, int64_t n64, int32_t s, int32_t dtype, const void* Z, void* Q,
+                         double* Cout) {
+    if (!c) return SKR_E_INVALID;
+    if (!Z || !Q || !Cout) return fail(c, SKR_E_INVALID, "null argument");
+    if (n64 < 1 || n64 > kMaxRows || s < 1 || s > kNoAllocMaxS || n64 < s)
+        return fail(c, SKR_E_INVALID, "skr_block_qr_noalloc needs 1 <= s <= 16 and s <= n <= 2^31 - 2^20 "
+                                      "(its static scratch holds the partials of s <= 16; use skr_block_qr)");
+    if (dtype != SKR_F64 && dtype != SKR_C64) return fail(c, SKR_E_INVALID, "bad dtype");
+    if (!c->scratch) return fail(c, SKR_E_HIP, "the static scratch array of this device could not be located");
+    return guarded(c, [&]() -> int {
+        SKR_HIP(hipSetDevice(c->device));
+        const int n = (int)n64;
+        const size_t bytes = (size_t)n * s * elt(dtype, false);
+        hipStream_t st = c->stream();
+        auto run = [&](auto tag) -> int {
+            using T = decltype(tag);
+            Env<T> e;
+            env_layout(e, n, s);
+            e.st = st;
+            // the QR's state in the static scratch: control block, coefficient
+            // slots, s x s partials of every workgroup and the second stage
+            const size_t ss = (size_t)s * s;
+            Arena ar;
+            ar.base = c->scratch;
+            ar.cap = kNoAllocBytes;
+            e.ctl = (Ctl*)ar.take(sizeof(Ctl));
+            e.hist = (double*)ar.take(4 * sizeof(double));
+            e.sc = (c64*)ar.take(sizeof(c64) * 128);
+            e.mats = (c64*)ar.take(sizeof(c64) * (size_t)M_COUNT * ss);
+            e.part = (c64*)ar.take(sizeof(c64) * (size_t)e.nb * ss);
+            e.part2 = (c64*)ar.take(sizeof(c64) * (size_t)e.p2 * ss);
+            if (ar.off > kNoAllocBytes) throw Unsupported{"scratch layout exceeds the static array"};
+            if (Q != Z) SKR_HIP(hipMemcpyAsync(Q, Z, bytes, hipMemcpyDeviceToDevice, st));
+            const bool ok = preprocess<T, 1>(c, e, (T*)Q);   // s <= 16: one 16-column tile
+            SKR_HIP(hipMemcpyAsync(c->hmat, e.mats + (size_t)M_RB * ss, sizeof(c64) * ss, hipMemcpyDeviceToHost,
+                                   st));
+            SKR_HIP(hipStreamSynchronize(st));
+            for (size_t k = 0; k < ss; ++k) {
+                if (dtype == SKR_C64) {
+                    Cout[2 * k] = c->hmat[k].x;
+                    Cout[2 * k + 1] = c->hmat[k].y;
+                } else {
+                    Cout[k] = c->hmat[k].x;
                 }
             }
             return ok ? SKR_OK : SKR_BREAKDOWN;
