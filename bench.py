@@ -62,30 +62,60 @@ def counter_traffic(kernel):
         return None
 
 
-def spmm_roofline(pkg, ctx, A, n, nnz, s, stream, reps=50):
-    """Average duration of the CSR sparse x block kernel (same launch
-    configuration as inside the solver) from HIP events on its stream."""
+def spmm_roofline(pkg, ctx, A, n, nnz, s, stream, reps=50, X=None, kernel="k_spmm_csr8<double,EpiNone>",
+                  adjoint=False):
+    """Average duration of the sparse x block kernel (same launch configuration
+    as inside the solver) from HIP events on its stream, against the
+    algorithmic bytes nnz (b + 4) + 4 (n + 1) + 2 n s b (b = 8 real, 16
+    complex FP64)."""
     import torch
-    X = torch.randn(n, s, dtype=torch.float64, device="cuda")
+    if X is None:
+        X = torch.randn(n, s, dtype=torch.float64, device="cuda")
     Y = torch.empty_like(X)
+    b = 16 if X.dtype == torch.complex128 else 8
     torch.cuda.synchronize()
     with torch.cuda.stream(stream):
         for _ in range(5):
-            pkg.spmm(ctx, A, X, Y, sync=False)
+            pkg.spmm(ctx, A, X, Y, adjoint=adjoint, sync=False)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         for _ in range(reps):
-            pkg.spmm(ctx, A, X, Y, sync=False)
+            pkg.spmm(ctx, A, X, Y, adjoint=adjoint, sync=False)
         e1.record(stream)
     e1.synchronize()
     ms = e0.elapsed_time(e1) / reps
-    bytes_alg = nnz * (8 + 4) + 4 * (n + 1) + 2 * n * s * 8
+    bytes_alg = nnz * (b + 4) + 4 * (n + 1) + 2 * n * s * b
     gbs = bytes_alg / (ms * 1e-3) / 1e9
-    kernel = "k_spmm_csr8<double,EpiNone>"
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": counter_traffic(kernel),
             "kernel": kernel, "avg_us": round(ms * 1e3, 2), "bytes_per_launch": bytes_alg}
+
+
+def spmm_only_config(pkg, inputs, k, fmt, stream, reps=20):
+    """The product with A of workload k (full size) alone, for kernel traces
+    and hardware counters: `reps` timed launches after 5 warm-ups, then 20
+    plain device copies of one n x s block (the counters' calibration)."""
+    import numpy as np
+    import torch
+    prob = inputs.config(k, "full")
+    ctx = pkg.Context(0, stream=stream.cuda_stream)
+    kw = dict(fmt="sell", sell_C=16, sell_sigma=256) if fmt == "sell" else {}
+    A = pkg.Matrix.from_csr(ctx, prob.A, **kw)
+    X = torch.from_numpy(np.ascontiguousarray(prob.B)).cuda()
+    n, s = X.shape
+    roof = spmm_roofline(pkg, ctx, A, n, prob.A.nnz, s, stream, reps=reps, X=X, kernel=f"config {k} {fmt}")
+    roof["traffic"] = None
+    C = torch.empty_like(X)
+    for _ in range(20):
+        C.copy_(X)
+    torch.cuda.synchronize()
+    out = {"workload": prob.name, "format": fmt, "n": n, "nnz": prob.A.nnz, "s": s,
+           "dtype": str(X.dtype).replace("torch.", ""), "spmm": roof,
+           "copy_bytes_per_launch": 2 * X.numel() * X.element_size()}
+    A.close()
+    ctx.close()
+    return out
 
 
 # iterations timed per method by the CPU baseline (20 in all), beyond one
@@ -413,7 +443,8 @@ def main():
                          "converging methods need 250-450 iterations here")
     ap.add_argument("--spmm-only", action="store_true",
                     help="only the sparse x block kernel and a plain device copy of one block "
-                         "(the workload of the hardware-counter runs)")
+                         "(the workload of the hardware-counter runs); with --config K, workload K "
+                         "(--format csr or sell: SELL-16-256)")
     ap.add_argument("--concurrent", type=int, default=1,
                     help="1 (default): the step's three solves run at the same time, each on its own "
                          "context, stream and host thread (same kernels and arithmetic, bit-identical "
@@ -450,7 +481,7 @@ def main():
     import inputs
     import paper_1504_04395_amd as pkg
 
-    if args.config:
+    if args.config and not args.spmm_only:
         ctx = pkg.Context(0)
         rows = config_solves(pkg, ctx, inputs, args.config, tuple(m for m in args.methods.split(",") if m),
                              args.precision, args.format, args.reps)
@@ -460,6 +491,11 @@ def main():
 
     if args.accel_ratio:
         print(json.dumps({"accel_ratio": accel_ratio(pkg, inputs)}), flush=True)
+        return
+
+    if args.spmm_only and args.config:
+        stream = torch.cuda.Stream()
+        print(json.dumps(spmm_only_config(pkg, inputs, args.config, args.format, stream)), flush=True)
         return
 
     if args.sell_sweep:

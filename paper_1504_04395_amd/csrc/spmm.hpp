@@ -335,13 +335,19 @@ __global__ __launch_bounds__(kBlock) void k_spmm_csr8(const Ctl* ctl, CsrOp<T> A
     // step's X gathers are in flight, so a step waits on one round of memory
     // instead of three.  Rows, entries and the order of the sums are those of
     // the plain sweep, so the result is the same to the bit.
+    // The row pointers are loaded unconditionally (rows past the end read the
+    // last row's, then discarded): a load under a branch makes the compiler wait
+    // for it at the branch's end, which would put one more memory round into
+    // every step.
     auto rows_of = [&](int base, int (&i)[2], bool (&valid)[2], int (&k0)[2], int (&k1)[2]) {
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
             i[p] = base + 16 * w + 8 * p + 2 * g + half;
             valid[p] = i[p] < r1;
-            k0[p] = valid[p] ? A.rp[i[p]] : 0;
-            k1[p] = valid[p] ? A.rp[i[p] + 1] : 0;
+            const int ii = min(i[p], A.n - 1);
+            const int a0 = A.rp[ii], a1 = A.rp[ii + 1];
+            k0[p] = valid[p] ? a0 : 0;
+            k1[p] = valid[p] ? a1 : 0;
         }
     };
     auto entries = [&](const int (&k0)[2], const int (&k1)[2], int off, int (&mc)[2], T (&ma)[2]) {

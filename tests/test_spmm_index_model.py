@@ -51,9 +51,10 @@ def walk_csr8(n, rp, s, nb):
     def rows_of(base, r1):
         i = np.stack([base + 16 * w + 8 * p + 2 * g + half for p in range(2)])
         valid = i < r1
-        assert np.all(i[valid] >= 0) and np.all(i[valid] + 1 <= n)      # rp[i], rp[i + 1]
-        k0 = np.where(valid, rp[np.where(valid, i, 0)], 0)
-        k1 = np.where(valid, rp[np.where(valid, i + 1, 0)], 0)
+        ii = np.minimum(i, n - 1)                                        # loaded for every lane
+        assert np.all(ii >= 0) and np.all(ii + 1 <= n)                   # rp[ii], rp[ii + 1]
+        k0 = np.where(valid, rp[ii], 0)
+        k1 = np.where(valid, rp[ii + 1], 0)
         return i, valid, k0, k1
 
     def entries(k0, k1, off):
