@@ -172,14 +172,19 @@ void spmm_j(Env<T>& e, const Operand<T>& op, const Layout& ly, const T* X, T* Y,
         }
     };
     if (op.sell) {
-        int nchunks = (e.n + op.sl.C - 1) / op.sl.C;
-        int cpb = (nchunks + e.nb - 1) / e.nb;
+        // 16 lanes per row, J16 = ceil(s / 16) columns per lane, one pass of 16
+        // sorted positions of a chunk per workgroup step
+        const int nchunks = (e.n + op.sl.C - 1) / op.sl.C;
+        const int cpb = (nchunks + e.nb - 1) / e.nb;
+        const Layout l16{ly.s, 16, 4};
         if constexpr (J16 == 2 && EpiIsGram<Epi>::value && J == 2) {
-            k_spmm_sell<T, J, EpiNone><<<e.nb, kBlock, 0, e.st>>>(ctl, op.sl, ly, cpb, X, Y, EpiNone{});
+            k_spmm_sell16<T, 2, EpiNone><<<e.nb, kBlock, 0, e.st>>>(ctl, op.sl, l16, cpb, X, Y, EpiNone{});
             SKR_LAUNCHED();
             gram_after(epi);
+        } else if constexpr (!EpiIsGram<Epi>::value || J == J16) {
+            k_spmm_sell16<T, J16, Epi><<<e.nb, kBlock, 0, e.st>>>(ctl, op.sl, l16, cpb, X, Y, epi);
         } else {
-            k_spmm_sell<T, J, Epi><<<e.nb, kBlock, 0, e.st>>>(ctl, op.sl, ly, cpb, X, Y, epi);
+            throw Unsupported{"Gram epilogue with a layout other than 16 lanes per row"};
         }
     } else if (!Tr<T>::cplx && J16 == 1 && ly.s % 2 == 0) {
         if constexpr (!Tr<T>::cplx && J16 == 1) {

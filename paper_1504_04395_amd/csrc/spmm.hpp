@@ -7,8 +7,8 @@
 //
 // SELL-C-sigma: rows are sorted by length inside windows of sigma rows and cut
 // into chunks of C rows; a chunk stores its entries column-major (slot k of all
-// C rows together), padded to the chunk's longest row.  A group of L lanes
-// still owns one row; the padding entries have value 0 and column = row.
+// C rows together), padded to the chunk's longest row.  16 lanes own one row
+// (k_spmm_sell16); the padding entries have value 0 and column = row.
 //
 // Epilogues fold the reductions the solvers need right after the product into
 // the same pass (the output row is still in registers): traces tr(Z^H Y),
@@ -235,8 +235,10 @@ __global__ __launch_bounds__(kBlock) void k_spmm_csr(const Ctl* ctl, CsrOp<T> A,
         for (int p = 0; p < RP; ++p) {
             i[p] = base + p * 16 + grp;
             valid[p] = i[p] < r1;
-            k0[p] = valid[p] ? A.rp[i[p]] : 0;
-            k1[p] = valid[p] ? A.rp[i[p] + 1] : 0;
+            const int ii = min(i[p], A.n - 1);      // unconditional loads: no wait at a branch join
+            const int a0 = A.rp[ii], a1 = A.rp[ii + 1];
+            k0[p] = valid[p] ? a0 : 0;
+            k1[p] = valid[p] ? a1 : 0;
         }
         T acc[RP][J];
 #pragma unroll
@@ -545,53 +547,162 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr(const Ctl* ctl, CsrOp<T> A,
     }
 }
 
+// Non-temporal load of one stored value (complex values as a 2-vector).
+template <class T> __device__ inline T nt_value(const T* p) { return __builtin_nontemporal_load(p); }
+template <> __device__ inline c64 nt_value<c64>(const c64* p) {
+    typedef double v2 __attribute__((ext_vector_type(2)));
+    const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+    return {v.x, v.y};
+}
+template <> __device__ inline c32 nt_value<c32>(const c32* p) {
+    typedef float v2 __attribute__((ext_vector_type(2)));
+    const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+    return {v.x, v.y};
+}
+
+// SELL-C-sigma product with the CSR kernels' techniques.  16 lanes per row
+// (lane l holds columns l + 16 j, j < J); a workgroup takes 16 consecutive
+// sorted positions of a chunk per pass (4 per wave) and walks its chunks in
+// order.  A chunk stores slot k of its rows contiguously, so the entries of a
+// wave's 4 rows for 8 slots are 32 loads of consecutive words (lanes 0..31),
+// staged in LDS and read back by the 16 lanes of each row (an LDS broadcast).
+// The sweep is software-pipelined: the next round's entries (next 8 slots,
+// or the first 8 of the next pass) are loaded while this round's X gathers
+// are in flight.  Padding slots (value 0, the row's own column) are gathered
+// and multiplied like stored entries; their terms are exact zeros.  Y is
+// written at the original row of each sorted position.
 template <class T, int J, class Epi>
-__global__ __launch_bounds__(kBlock) void k_spmm_sell(const Ctl* ctl, SellOp<T> A, Layout ly, int chunks_per_block,
-                                                       const T* __restrict__ X, T* __restrict__ Y, Epi epi) {
+__global__ __launch_bounds__(kBlock) void k_spmm_sell16(const Ctl* ctl, SellOp<T> A, Layout ly, int chunks_per_block,
+                                                         const T* __restrict__ X, T* __restrict__ Y, Epi epi) {
     if (stopped(ctl)) return;
-    const int tid = threadIdx.x;
-    const int lane = tid & (ly.L - 1);
-    const int grp = tid >> ly.lgL;
-    const int rpb = kBlock >> ly.lgL;
-    const int s = ly.s;
-    const int nchunks = (A.n + A.C - 1) / A.C;
+    constexpr int U = 8;
+    const int lane = threadIdx.x & 15, rr = (threadIdx.x >> 4) & 3, w = threadIdx.x >> 6, lw = threadIdx.x & 63;
+    const int s = ly.s, C = A.C;
+    const int nchunks = (A.n + C - 1) / C;
     const int cb = xcd_chunk(blockIdx.x, gridDim.x) * chunks_per_block;
     const int ce = min(nchunks, cb + chunks_per_block);
-    const int pb = cb * A.C;
-    const int pe = min(A.n, ce * A.C);
+    __shared__ __align__(16) int ecol[kWaves][U][4];
+    __shared__ __align__(16) T eval[kWaves][U][4];
+    int col[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) col[j] = min(lane + 16 * j, s - 1);
     typename Epi::St st;
     epi.init(st);
-    for (int base = pb; base < pe; base += rpb) {
-        const int p = base + grp;                // sorted position
-        const bool valid = p < pe;
-        T acc[J];
+    // a round: chunk ch, pass r0 (rows r0 .. r0 + 15 of the chunk), slots k .. k + U - 1
+    struct Round { int ch, r0, k, width, e0; };
+    auto chunk_round = [&](int ch) {
+        Round q{ch, 0, 0, 0, 0};
+        if (ch < ce) {
+            q.width = A.clen[ch];
+            q.e0 = A.cptr[ch];
+        }
+        return q;
+    };
+    auto next_round = [&](Round q) {
+        q.k += U;
+        if (q.k >= q.width) {
+            q.k = 0;
+            q.r0 += 16;
+            if (q.r0 >= C) q = chunk_round(q.ch + 1);
+        }
+        return q;
+    };
+    // lane lw < 32 loads slot k + lw / 4 of row r0 + 4 w + lw % 4; other lanes and
+    // slots past the chunk's width read slot 0 of the array (always allocated)
+    // with value 0
+    auto load_round = [&](const Round& q, int& mc, T& ma) {
+        const int kk = q.k + (lw >> 2);
+        const bool ok = q.ch < ce && lw < 32 && kk < q.width;
+        const int e = ok ? q.e0 + kk * C + q.r0 + 4 * w + (lw & 3) : 0;
+        mc = __builtin_nontemporal_load(&A.ci[e]);
+        const T v = nt_value(&A.va[e]);
+        ma = ok ? v : zero<T>();
+    };
+    Round cur = chunk_round(cb);
+    while (cur.ch < ce && cur.width == 0) {   // chunks of empty rows: write zeros
+        for (int r0 = 0; r0 < C; r0 += 16) {
+            const int pos = cur.ch * C + r0 + 4 * w + rr;
+            const bool valid = pos < A.n;
+            T acc[J];
 #pragma unroll
-        for (int j = 0; j < J; ++j) acc[j] = zero<T>();
-        int i = 0;
-        if (valid) {
-            const int ch = p / A.C;
-            const int r = p - ch * A.C;
-            i = A.row[p];
-            const int w = A.clen[ch];
-            const int e0 = A.cptr[ch] + r;
-            for (int k = 0; k < w; ++k) {
-                const int e = e0 + k * A.C;
-                const int c = A.ci[e];
-                const T a = A.va[e];
-                const T* __restrict__ xr = X + (size_t)c * s;
+            for (int j = 0; j < J; ++j) acc[j] = zero<T>();
+            const int i = valid ? A.row[pos] : 0;
+            if (valid) {
 #pragma unroll
-                for (int j = 0; j < J; ++j) {
-                    int col = lane + ly.L * j;
-                    if (col < s) acc[j] = fma_(a, xr[col], acc[j]);
-                }
+                for (int j = 0; j < J; ++j)
+                    if (lane + 16 * j < s) Y[(size_t)i * s + lane + 16 * j] = acc[j];
             }
+            epi.row(st, i, valid, lane, ly, acc);
+        }
+        cur = chunk_round(cur.ch + 1);
+    }
+    int mc = 0;
+    T ma = zero<T>();
+    if (cur.ch < ce) load_round(cur, mc, ma);
+    T acc[J];
 #pragma unroll
-            for (int j = 0; j < J; ++j) {
-                int col = lane + ly.L * j;
-                if (col < s) Y[(size_t)i * s + col] = acc[j];
+    for (int j = 0; j < J; ++j) acc[j] = zero<T>();
+    while (cur.ch < ce) {
+        if (lw < 32) {                            // lanes 0..31 hold this round's entries
+            ecol[w][lw >> 2][lw & 3] = mc;
+            eval[w][lw >> 2][lw & 3] = ma;
+        }
+        __builtin_amdgcn_wave_barrier();
+        int cc[U];
+        T av[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) cc[u] = ecol[w][u][rr];
+        T xv[U][J];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int j = 0; j < J; ++j) xv[u][j] = X[(size_t)cc[u] * s + col[j]];
+        Round nxt = next_round(cur);
+        int nmc = 0;
+        T nma = zero<T>();
+        if (nxt.ch < ce) load_round(nxt, nmc, nma);     // next round's entries, behind the gathers
+#pragma unroll
+        for (int u = 0; u < U; ++u) av[u] = eval[w][u][rr];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int j = 0; j < J; ++j) acc[j] = fma_(av[u], xv[u][j], acc[j]);
+        __builtin_amdgcn_wave_barrier();                 // every read of this round precedes the next writes
+        if (nxt.ch != cur.ch || nxt.r0 != cur.r0) {      // the pass ends: store its rows
+            const int pos = cur.ch * C + cur.r0 + 4 * w + rr;
+            const bool valid = pos < A.n;
+            const int i = valid ? A.row[pos] : 0;
+            if (valid) {
+#pragma unroll
+                for (int j = 0; j < J; ++j)
+                    if (lane + 16 * j < s) Y[(size_t)i * s + lane + 16 * j] = acc[j];
+            }
+            epi.row(st, i, valid, lane, ly, acc);
+#pragma unroll
+            for (int j = 0; j < J; ++j) acc[j] = zero<T>();
+            // chunks of empty rows after this one
+            while (nxt.ch < ce && nxt.width == 0) {
+                for (int r0 = 0; r0 < C; r0 += 16) {
+                    const int p2 = nxt.ch * C + r0 + 4 * w + rr;
+                    const bool v2 = p2 < A.n;
+                    T z[J];
+#pragma unroll
+                    for (int j = 0; j < J; ++j) z[j] = zero<T>();
+                    const int i2 = v2 ? A.row[p2] : 0;
+                    if (v2) {
+#pragma unroll
+                        for (int j = 0; j < J; ++j)
+                            if (lane + 16 * j < s) Y[(size_t)i2 * s + lane + 16 * j] = z[j];
+                    }
+                    epi.row(st, i2, v2, lane, ly, z);
+                }
+                nxt = chunk_round(nxt.ch + 1);
+                if (nxt.ch < ce) load_round(nxt, nmc, nma);
             }
         }
-        epi.row(st, i, valid, lane, ly, acc);
+        cur = nxt;
+        mc = nmc;
+        ma = nma;
     }
     epi_finish<Epi, J>(epi, st, blockIdx.x, s);
 }

@@ -96,8 +96,10 @@ def test_two_solves_share_one_matrix(env):
 @pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
 @pytest.mark.parametrize("grid", [64, 1024])
 def test_gradient_matches_finite_differences(env, grid, precision):
-    """Central differences of L with solves at 1e-12 (with FP32 inner solves,
-    1e-12 is the outer FP64 refinement's target).  Along F (on B) central
+    """Central differences of L with solves at 1e-12 in FP64.  With FP32 inner
+    solves the outer FP64 refinement targets 1e-11: on the 1024 x 1024 adjoint
+    system it stagnates near 3e-12 (30 outer steps measured), and 1e-11 still
+    leaves the solve error far below the 1e-6 bar.  Along F (on B) central
     differences are exact, since L is quadratic in B.  Along E (on A's stored
     values) the step is swept over relative sizes 1e-7..1e-10 (kappa(A) grows
     like the grid size squared, so a larger step leaves the linear regime);
@@ -110,14 +112,15 @@ def test_gradient_matches_finite_differences(env, grid, precision):
     rng = np.random.default_rng(3)
     E = rng.standard_normal(A.nnz)
     F = rng.standard_normal(B.shape)
-    L0, gv, gB, _ = _loss_and_grads(P, ctx, A, B, Xt, "egl_bicg", precision, 1e-12)
+    tol = 1e-12 if precision == "fp64" else 1e-11
+    L0, gv, gB, _ = _loss_and_grads(P, ctx, A, B, Xt, "egl_bicg", precision, tol)
     M = P.Matrix.from_csr(ctx, A)
     Xtt = torch.tensor(Xt, device="cuda")
 
     def loss(hE, hF):
         vals = torch.tensor(A.data + hE * E, device="cuda")
         Bt = torch.tensor(B + hF * F, device="cuda")
-        X = P.sparse_solve(vals, Bt, M, "egl_bicg", 1e-12, precision)
+        X = P.sparse_solve(vals, Bt, M, "egl_bicg", tol, precision)
         return float(((X - Xtt) ** 2).sum())
 
     hF = 1e-3 * np.linalg.norm(B) / np.linalg.norm(F)

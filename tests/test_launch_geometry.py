@@ -92,25 +92,75 @@ def test_no_int32_overflow_at_the_row_limit(s):
         assert ((nb - 1) * cpb + cpb) * C + BLOCK <= INT32_MAX
 
 
-@pytest.mark.parametrize("n", [1, 17, 1000, 65_536 + 9])
-@pytest.mark.parametrize("C", [16, 32, 64])
-@pytest.mark.parametrize("L", [1, 4, 16])
-def test_sell_chunk_walk_covers_every_position_once(n, C, L):
-    """k_spmm_sell: workgroup b owns chunks [xcd_chunk(b) * cpb, +cpb) and walks
-    their sorted positions in passes of BLOCK / L rows."""
-    nb, _, _, _, _ = env(n, 1)
-    nchunks = (n + C - 1) // C
+def _sell_layout(lens, C, sigma):
+    """Chunk widths and offsets of SELL-C-sigma by its definition (rows sorted by
+    length, longest first, inside windows of sigma rows; chunks of C sorted
+    positions padded to their longest row)."""
+    n = lens.size
+    order = np.concatenate([w0 + np.argsort(-lens[w0:w0 + sigma], kind="stable") for w0 in range(0, n, sigma)])
+    nch = (n + C - 1) // C
+    clen = np.array([lens[order[c * C:(c + 1) * C]].max(initial=0) for c in range(nch)], dtype=np.int64)
+    cptr = np.concatenate([[0], np.cumsum(clen * C)])
+    return clen, cptr
+
+
+def walk_sell16(n, lens, C, sigma, nb):
+    """Model of k_spmm_sell16's walk: workgroup b owns chunks [xcd_chunk(b) * cpb,
+    +cpb); rounds (chunk, pass r0, slot k) advance by 8 slots, then by 16 sorted
+    positions, then to the next chunk; chunks of width 0 only write zeros.  Lane
+    lw < 32 of wave w loads slot k + lw // 4 of position r0 + 4 w + lw % 4.
+    Returns (writes per sorted position, loads per stored slot, max load index)."""
+    U = 8
+    clen, cptr = _sell_layout(lens, C, sigma)
+    slots = int(cptr[-1])
+    nchunks = clen.size
     cpb = (nchunks + nb - 1) // nb
-    rpb = BLOCK // L
-    seen = np.zeros(n, dtype=np.int64)
+    writes = np.zeros(n, dtype=np.int64)
+    loads = np.zeros(max(slots, 1), dtype=np.int64)
+    lw = np.arange(32)
     for b in range(nb):
         cb = xcd_chunk(b, nb) * cpb
         ce = min(nchunks, cb + cpb)
-        pb, pe = cb * C, min(n, ce * C)
-        for base in range(pb, pe, rpb):
-            p = base + np.arange(rpb)
-            seen[p[p < pe]] += 1
-    assert np.all(seen == 1)
+        for ch in range(cb, ce):
+            width, e0 = int(clen[ch]), int(cptr[ch])
+            for r0 in range(0, C, 16):
+                for w in range(4):
+                    pos = ch * C + r0 + 4 * w + np.arange(4)
+                    writes[pos[pos < n]] += 1
+                    for k in range(0, width, U):                   # no rounds in a width-0 chunk
+                        kk = k + (lw >> 2)
+                        ok = kk < width
+                        e = np.where(ok, e0 + kk * C + r0 + 4 * w + (lw & 3), 0)
+                        assert np.all((e >= 0) & (e < max(slots, 1)))
+                        assert np.all((lw >> 2) < U) and np.all((lw & 3) < 4)   # LDS [8][4] per wave
+                        np.add.at(loads, e[ok], 1)
+    return writes, loads, slots
+
+
+@pytest.mark.parametrize("n", [1, 17, 1000, 20_000 + 9])
+@pytest.mark.parametrize("C", [16, 32, 64])
+@pytest.mark.parametrize("sigma_mult", [1, 16])
+def test_sell16_walk_writes_every_position_once_and_loads_every_slot_once(n, C, sigma_mult):
+    """k_spmm_sell16 on ragged rows (empty rows, long rows, a partial last chunk,
+    chunks of empty rows): every sorted position is written once and every
+    stored slot (padding included) is loaded exactly once, all in bounds."""
+    rng = np.random.default_rng(n + C)
+    lens = rng.integers(0, 12, size=n)
+    lens[rng.random(n) < 0.2] = 0
+    if n > 40:
+        lens[rng.choice(n, 3, replace=False)] = 37
+        lens[: 2 * C] = 0                                   # whole chunks of empty rows
+    nb = env(n, 1)[0]
+    writes, loads, slots = walk_sell16(n, lens, C, C * sigma_mult, nb)
+    assert np.all(writes == 1)
+    if slots:
+        assert np.all(loads == 1)
+
+
+def test_sell16_all_empty_matrix():
+    n, C = 100, 16
+    writes, loads, slots = walk_sell16(n, np.zeros(n, dtype=np.int64), C, 256, env(n, 1)[0])
+    assert slots == 0 and np.all(writes == 1)
 
 
 def _per_xcd_sweep(n, nb, per_xcd, rows_per_pass, row_of):
