@@ -96,10 +96,11 @@ def test_two_solves_share_one_matrix(env):
 @pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
 @pytest.mark.parametrize("grid", [64, 1024])
 def test_gradient_matches_finite_differences(env, grid, precision):
-    """Central differences of L with solves at 1e-12 in FP64.  With FP32 inner
-    solves the outer FP64 refinement targets 1e-11: on the 1024 x 1024 adjoint
-    system it stagnates near 3e-12 (30 outer steps measured), and 1e-11 still
-    leaves the solve error far below the 1e-6 bar.  Along F (on B) central
+    """Central differences of L with solves at 1e-12.  With FP32 inner solves
+    on the 1024 x 1024 grid the outer FP64 refinement targets 1e-11: on that
+    adjoint system it stagnates near 3e-12 (30 outer steps measured), and 1e-11
+    still leaves the solve error far below the 1e-6 bar there (on the 64 x 64
+    grid 1e-11 is not enough for the A direction: best step 1.4e-6).  Along F (on B) central
     differences are exact, since L is quadratic in B.  Along E (on A's stored
     values) the step is swept over relative sizes 1e-7..1e-10 (kappa(A) grows
     like the grid size squared, so a larger step leaves the linear regime);
@@ -112,7 +113,7 @@ def test_gradient_matches_finite_differences(env, grid, precision):
     rng = np.random.default_rng(3)
     E = rng.standard_normal(A.nnz)
     F = rng.standard_normal(B.shape)
-    tol = 1e-12 if precision == "fp64" else 1e-11
+    tol = 1e-11 if (precision == "fp32_refine" and grid >= 1024) else 1e-12
     L0, gv, gB, _ = _loss_and_grads(P, ctx, A, B, Xt, "egl_bicg", precision, tol)
     M = P.Matrix.from_csr(ctx, A)
     Xtt = torch.tensor(Xt, device="cuda")
