@@ -267,9 +267,12 @@ def paper_table2(pkg, ctx, inputs, reps=3, examples=(1, 2, 3), preconds=(None, "
     return rows
 
 
-def config_solves(pkg, ctx, inputs, k, methods, precision, fmt, reps):
+def config_solves(pkg, ctx, inputs, k, methods, precision, fmt, reps, inner_tol=1e-4, max_outer=20):
     """Solve workload k of inputs.config (full size) with each method to 1e-8
-    (at most 3000 iterations); the best of `reps` timed solves per method."""
+    (at most 3000 iterations); the best of `reps` timed solves per method.  With
+    FP32 inner solves, `inner_tol` and `max_outer` set the refinement, and the
+    record carries the true relative residual before each outer step and
+    after the last."""
     import numpy as np
     import torch
     prob = inputs.config(k, "full")
@@ -277,7 +280,7 @@ def config_solves(pkg, ctx, inputs, k, methods, precision, fmt, reps):
     A = pkg.Matrix.from_csr(ctx, prob.A, fmt=fmt, make_fp32=precision != "fp64")
     B = torch.from_numpy(np.ascontiguousarray(prob.B)).cuda()
     X = torch.zeros_like(B)
-    kw = {} if precision == "fp64" else dict(precision=precision, inner_tol=1e-4, max_outer=20)
+    kw = {} if precision == "fp64" else dict(precision=precision, inner_tol=inner_tol, max_outer=max_outer)
     rows = []
     for m in methods or prob.methods:
         best = None
@@ -288,9 +291,13 @@ def config_solves(pkg, ctx, inputs, k, methods, precision, fmt, reps):
             torch.cuda.synchronize()
             dt = time.perf_counter() - t
             best = dt if best is None else min(best, dt)
-        rows.append({"workload": prob.name, "format": fmt, "precision": precision, "method": m,
-                     "status": info.status_name, "iterations": info.iterations,
-                     "outer": info.outer_iterations, "rel_res_true": info.rel_res_true, "seconds": round(best, 4)})
+        row = {"workload": prob.name, "format": fmt, "precision": precision, "method": m,
+               "status": info.status_name, "iterations": info.iterations,
+               "outer": info.outer_iterations, "rel_res_true": info.rel_res_true, "seconds": round(best, 4)}
+        if precision != "fp64":
+            row.update(inner_tol=inner_tol, max_outer=max_outer, outer_redone_in_fp64=info.fp64_outer_iterations,
+                       outer_history=[float(f"{h:.3e}") for h in info.history])
+        rows.append(row)
         log(f"{m}: {info.status_name} it={info.iterations} {best * 1e3:.1f} ms")
     A.close()
     return rows
@@ -461,6 +468,8 @@ def main():
                     help="instead of the benchmark: solve workload K of inputs.config at full size with "
                          "--methods (default: the workload's own list)")
     ap.add_argument("--precision", default="fp64", help="with --config: fp64 or fp32_refine")
+    ap.add_argument("--inner-tol", type=float, default=1e-4, help="with --config and fp32_refine: inner tolerance")
+    ap.add_argument("--max-outer", type=int, default=20, help="with --config and fp32_refine: outer step cap")
     ap.add_argument("--format", default="csr", help="with --config: csr or sell")
     ap.add_argument("--accel-ratio", action="store_true",
                     help="instead of the benchmark: Table 1's blocking gain a (s vector products over one "
@@ -484,7 +493,7 @@ def main():
     if args.config and not args.spmm_only:
         ctx = pkg.Context(0)
         rows = config_solves(pkg, ctx, inputs, args.config, tuple(m for m in args.methods.split(",") if m),
-                             args.precision, args.format, args.reps)
+                             args.precision, args.format, args.reps, args.inner_tol, args.max_outer)
         print(json.dumps({"config_solves": rows}), flush=True)
         ctx.close()
         return
