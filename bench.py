@@ -303,6 +303,29 @@ def config_solves(pkg, ctx, inputs, k, methods, precision, fmt, reps, inner_tol=
     return rows
 
 
+def perturbed_counts(pkg, inputs, grid, seeds, maxit):
+    """The benchmark's three solves on B and on B perturbed by 1e-15 relative
+    noise (numpy default_rng(seed), the recipe of the oracle's count file):
+    the GPU's own iteration-count spread under rounding-level changes."""
+    import numpy as np
+    import torch
+    A_csr = inputs.convdiff3d(grid, (30.0, 20.0, 10.0))
+    B0 = inputs.gaussian_block(A_csr.n, 16, seed=0)
+    ctx = pkg.Context(0)
+    A = pkg.Matrix.from_csr(ctx, A_csr)
+    out = {m: {} for m in METHODS}
+    for seed in [0] + list(seeds):
+        Bs = B0 if seed == 0 else B0 * (1 + 1e-15 * np.random.default_rng(seed).standard_normal(B0.shape))
+        B = torch.from_numpy(np.ascontiguousarray(Bs)).cuda()
+        for m in METHODS:
+            _, info = pkg.solve(ctx, A, B, m, tol=1e-8, maxit=maxit)
+            out[m][seed] = {"iterations": info.iterations, "status": info.status_name}
+        log(f"seed {seed}: " + ", ".join(f"{m} {out[m][seed]['iterations']}" for m in METHODS))
+    A.close()
+    ctx.close()
+    return {"workload": f"convdiff3d-{grid}^3-s16", "tol": 1e-8, "maxit": maxit, "counts": out}
+
+
 def config1_latency(pkg, inputs, reps=7):
     """The small 2D workload (32 x 32 grid, n = 1024, s = 4, FP64): Gl-BiCG and
     eGl-BiCG to 1e-8 with the iteration captured in a hipGraph and launched
@@ -475,6 +498,9 @@ def main():
                     help="instead of the benchmark: Table 1's blocking gain a (s vector products over one "
                          "block product) on workloads 2-5 at full size")
     ap.add_argument("--no-config1", action="store_true", help="skip the small-workload latency figures")
+    ap.add_argument("--perturbed-counts", type=int, default=0,
+                    help="instead of the benchmark: iteration counts of the three solves on B and on K copies "
+                         "perturbed by 1e-15 (seeds 1..K)")
     ap.add_argument("--sell-sweep", action="store_true",
                     help="instead of the benchmark: the sparse x block product on the power-law workload "
                          "in CSR and SELL-C-sigma (C in 16, 32, 64; sigma in C, 256, 1024, 8192)")
@@ -500,6 +526,12 @@ def main():
 
     if args.accel_ratio:
         print(json.dumps({"accel_ratio": accel_ratio(pkg, inputs)}), flush=True)
+        return
+
+    if args.perturbed_counts:
+        print(json.dumps({"perturbed_counts": perturbed_counts(pkg, inputs, args.grid,
+                                                               range(1, args.perturbed_counts + 1), args.maxit)}),
+              flush=True)
         return
 
     if args.spmm_only and args.config:
