@@ -328,9 +328,11 @@ def perturbed_counts(pkg, inputs, grid, seeds, maxit):
 
 def config1_latency(pkg, inputs, reps=7):
     """The small 2D workload (32 x 32 grid, n = 1024, s = 4, FP64): Gl-BiCG and
-    eGl-BiCG to 1e-8 with the iteration captured in a hipGraph and launched
-    eagerly; the median solve time of `reps`, microseconds per iteration, and
-    the oracle's full solve in seconds (untuned, on the host)."""
+    eGl-BiCG to 1e-8 on the single-workgroup path (every iteration in one
+    launch, the default for this size) and on the general schedule with the
+    iteration captured in a hipGraph and launched eagerly; the median solve
+    time of `reps`, microseconds per iteration, and the oracle's full solve in
+    seconds (untuned, on the host)."""
     import numpy as np
     import torch
     import oracle
@@ -342,24 +344,25 @@ def config1_latency(pkg, inputs, reps=7):
     rows = {}
     for m in ("gl_bicg", "egl_bicg"):
         r = {}
-        for graph in (True, False):
+        for mode, fused, graph in (("fused", True, True), ("graph", False, True), ("eager", False, False)):
             ts = []
             for _ in range(reps + 1):
                 torch.cuda.synchronize()
                 t = time.perf_counter()
-                _, info = pkg.solve(ctx, A, B, m, X=X, x0_zero=True, tol=1e-8, use_graph=graph)
+                _, info = pkg.solve(ctx, A, B, m, X=X, x0_zero=True, tol=1e-8, use_graph=graph, fused_small=fused)
                 torch.cuda.synchronize()
                 ts.append(time.perf_counter() - t)
             med = float(np.median(ts[1:]))      # the first solve also builds the graph
-            r["graph" if graph else "eager"] = {"ms_per_solve": round(med * 1e3, 3),
+            r[mode] = {"ms_per_solve": round(med * 1e3, 3),
                                                 "us_per_iteration": round(med * 1e6 / info.iterations, 2),
                                                 "iterations": info.iterations, "status": info.status_name}
         t = time.perf_counter()
         ref = oracle.solve(prob.A, prob.B, m, tol=1e-8)
         r["oracle"] = {"s_per_solve": round(time.perf_counter() - t, 4), "iterations": ref.iterations}
         rows[m] = r
-        log(f"config 1 {m}: graph {r['graph']['us_per_iteration']} us/it, eager {r['eager']['us_per_iteration']} "
-            f"us/it, oracle {r['oracle']['s_per_solve']} s")
+        log(f"config 1 {m}: fused {r['fused']['us_per_iteration']} us/it ({r['fused']['ms_per_solve']} ms), "
+            f"graph {r['graph']['us_per_iteration']} us/it, eager {r['eager']['us_per_iteration']} us/it, "
+            f"oracle {r['oracle']['s_per_solve']} s")
     A.close()
     ctx.close()
     return {"workload": prob.name, "n": prob.A.n, "s": int(prob.B.shape[1]), "tol": 1e-8, "methods": rows}
@@ -498,6 +501,8 @@ def main():
                     help="instead of the benchmark: Table 1's blocking gain a (s vector products over one "
                          "block product) on workloads 2-5 at full size")
     ap.add_argument("--no-config1", action="store_true", help="skip the small-workload latency figures")
+    ap.add_argument("--config1-only", action="store_true",
+                    help="instead of the benchmark: only the small-workload latency figures")
     ap.add_argument("--perturbed-counts", type=int, default=0,
                     help="instead of the benchmark: iteration counts of the three solves on B and on K copies "
                          "perturbed by 1e-15 (seeds 1..K)")
@@ -515,6 +520,10 @@ def main():
 
     import inputs
     import paper_1504_04395_amd as pkg
+
+    if args.config1_only:
+        print(json.dumps({"config1_latency": config1_latency(pkg, inputs)}), flush=True)
+        return
 
     if args.config and not args.spmm_only:
         ctx = pkg.Context(0)

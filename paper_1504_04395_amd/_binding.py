@@ -34,7 +34,7 @@ class skr_opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int32), ("preprocess_qr", ctypes.c_int32),
                 ("zero_x0", ctypes.c_int32), ("check_every", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("precond", ctypes.c_int32)]
+                ("precond", ctypes.c_int32), ("fused_small", ctypes.c_int32)]
 
 
 class skr_result(ctypes.Structure):
@@ -313,11 +313,13 @@ def solve(ctx: Context, A: Matrix, B, method: str, X=None, x0_zero: bool = False
           maxit: int = 10000,
           precision: str = "fp64", inner_tol: float = 1e-4, max_outer: int = 10, preprocess_qr: bool = True,
           check_every: int = 16, use_graph: bool = True, adjoint: bool = False, history_cap: int | None = None,
-          precond: str | None = None):
+          precond: str | None = None, fused_small: bool = True):
     """skr_solve.  B: n x s (numpy or torch CUDA tensor).  X: optional initial
     guess / output array of the same kind (a new one is created if None);
     with x0_zero the contents of X are ignored (X0 = 0).  precond='ilu0':
-    right ILU(0) preconditioning (A.ilu0() first).  Returns (X, SolveInfo)."""
+    right ILU(0) preconditioning (A.ilu0() first).  fused_small=False keeps
+    small Gl-BiCG / eGl-BiCG systems on the general multi-kernel schedule.
+    Returns (X, SolveInfo)."""
     lib = load_library()
     _check_block(B, A.n, A.dtype, "B")
     if X is not None:
@@ -350,6 +352,7 @@ def solve(ctx: Context, A: Matrix, B, method: str, X=None, x0_zero: bool = False
     o.check_every = check_every
     o.use_graph = int(use_graph)
     o.precond = PRECONDS[precond]
+    o.fused_small = int(fused_small)
     cap = history_cap if history_cap is not None else maxit + 2
     hist = np.zeros(max(cap, 1), dtype=np.float64)
     r = skr_result()

@@ -22,6 +22,7 @@
 #include "engine.hpp"
 #include "csr_host.hpp"
 #include "sell.hpp"
+#include "smallsys.hpp"
 
 using namespace skr;
 
@@ -165,6 +166,7 @@ struct skr_context {
     c64* hsum = nullptr;  // pinned, small
     c64* hmat = nullptr;  // pinned, kMaxS x kMaxS: s x s results of the allocation-free calls
     char* scratch = nullptr;   // device address of this device's static scratch array (or null)
+    int lds_max = 0;           // LDS bytes one workgroup may hold on this device
     std::vector<GraphEntry> graphs;
     std::vector<skr_matrix*> mats;   // live matrices (orphaned when the context goes first)
     void* stage = nullptr;           // cached staging blocks for B and X (grow-only)
@@ -487,6 +489,21 @@ struct InnerStats {
     std::vector<double> hist;
 };
 
+// Stop state (already copied to c->hout) and history of a finished run.
+template <class T>
+InnerStats inner_stats(skr_context* c, Env<T>& e, long long mv_per_iter) {
+    InnerStats r;
+    const Ctl& o = *c->hout;
+    r.iters = o.iter;
+    r.bd_iter = o.bd_iter;
+    r.status = o.status == ST_OK ? SKR_OK : (o.status == ST_BREAKDOWN ? SKR_BREAKDOWN : SKR_NOT_CONVERGED);
+    r.matvecs = (long long)o.iter * mv_per_iter;
+    r.rres = o.nr0 > 0 ? o.res / o.nr0 : 0.0;
+    r.hist.resize((size_t)o.iter + 1);
+    SKR_HIP(hipMemcpy(r.hist.data(), e.hist, sizeof(double) * r.hist.size(), hipMemcpyDeviceToHost));
+    return r;
+}
+
 // Run a method to completion on A D = rhs (the caller enqueued rhs).
 template <class T>
 InnerStats iterate(skr_context* c, Env<T>& e, Method<T>& m, int method, double tol, int maxit, int every,
@@ -548,16 +565,72 @@ InnerStats iterate(skr_context* c, Env<T>& e, Method<T>& m, int method, double t
         SKR_HIP(hipStreamSynchronize(e.st));
         if (c->hout->done || launched > cap) break;
     }
-    InnerStats r;
-    const Ctl& o = *c->hout;
-    r.iters = o.iter;
-    r.bd_iter = o.bd_iter;
-    r.status = o.status == ST_OK ? SKR_OK : (o.status == ST_BREAKDOWN ? SKR_BREAKDOWN : SKR_NOT_CONVERGED);
-    r.matvecs = (long long)o.iter * m.mv_per_iter;
-    r.rres = o.nr0 > 0 ? o.res / o.nr0 : 0.0;
-    r.hist.resize((size_t)o.iter + 1);
-    SKR_HIP(hipMemcpy(r.hist.data(), e.hist, sizeof(double) * r.hist.size(), hipMemcpyDeviceToHost));
-    return r;
+    return inner_stats(c, e, m.mv_per_iter);
+}
+
+// Dynamic LDS of the single-workgroup Gl-BiCG / eGl-BiCG kernel: P (n x s),
+// then P^ (n x s) or p^ (n).
+template <class T>
+size_t small_lds_bytes(int n, int s, bool econ) {
+    return sizeof(T) * ((size_t)n * s + (econ ? (size_t)n : (size_t)n * s));
+}
+
+// A system the single-workgroup kernel takes: Gl-BiCG or eGl-BiCG, CSR
+// operands, no preconditioner, n <= 1024 rows, s within the register budget
+// and both LDS blocks within one workgroup's LDS (with 1 KiB left for the
+// kernel's reduction slots).
+template <class T>
+bool small_eligible(const skr_context* c, const Env<T>& e, int method, const skr_opts& o) {
+    if (!o.fused_small || (method != SKR_GL_BICG && method != SKR_EGL_BICG)) return false;
+    if (e.n < 1 || e.n > kSmallMaxRows || e.s > SmallMaxS<T>::value || e.A.sell || e.AH.sell || e.pc) return false;
+    return small_lds_bytes<T>(e.n, e.s, method == SKR_EGL_BICG) + 1024 <= (size_t)c->lds_max;
+}
+
+template <class T, int S>
+void launch_small(Env<T>& e, bool econ, size_t lds, const T* rhs, T* D) {
+    if (econ) {
+        SKR_HIP(hipFuncSetAttribute((const void*)k_small_bicg<T, true, S>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        k_small_bicg<T, true, S><<<1, kSmallThreads, lds, e.st>>>(e.ctl, e.hist, e.A.csr, e.AH.csr, rhs, D);
+    } else {
+        SKR_HIP(hipFuncSetAttribute((const void*)k_small_bicg<T, false, S>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        k_small_bicg<T, false, S><<<1, kSmallThreads, lds, e.st>>>(e.ctl, e.hist, e.A.csr, e.AH.csr, rhs, D);
+    }
+}
+
+// Run Gl-BiCG or eGl-BiCG on A D = rhs in one launch (every iteration inside
+// one workgroup); same stopping rule, breakdown rules and history as iterate.
+template <class T>
+InnerStats iterate_small(skr_context* c, Env<T>& e, int method, double tol, int maxit, const T* rhs, T* D) {
+    Ctl* h = c->hin;
+    std::memset(h, 0, sizeof(Ctl));
+    h->status = ST_RUNNING;
+    h->bd_iter = -1;
+    h->maxit = maxit;
+    h->tol = tol;
+    SKR_HIP(hipMemcpyAsync(e.ctl, h, sizeof(Ctl), hipMemcpyHostToDevice, e.st));
+    const bool econ = method == SKR_EGL_BICG;
+    const size_t lds = small_lds_bytes<T>(e.n, e.s, econ);
+    if constexpr (Tr<T>::cplx) {
+        switch (e.s) {
+            case 1: launch_small<T, 1>(e, econ, lds, rhs, D); break;
+            case 2: launch_small<T, 2>(e, econ, lds, rhs, D); break;
+            default: throw Unsupported{"single-workgroup path: block too wide"};
+        }
+    } else {
+        switch (e.s) {
+            case 1: launch_small<T, 1>(e, econ, lds, rhs, D); break;
+            case 2: launch_small<T, 2>(e, econ, lds, rhs, D); break;
+            case 3: launch_small<T, 3>(e, econ, lds, rhs, D); break;
+            case 4: launch_small<T, 4>(e, econ, lds, rhs, D); break;
+            default: throw Unsupported{"single-workgroup path: block too wide"};
+        }
+    }
+    SKR_LAUNCHED();
+    SKR_HIP(hipMemcpyAsync(c->hout, e.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, e.st));
+    SKR_HIP(hipStreamSynchronize(e.st));
+    return inner_stats(c, e, econ ? (long long)e.s + 1 : 2LL * e.s);
 }
 
 // True residual: part = (||B - A X||^2, ||B||^2) -> host
@@ -648,8 +721,10 @@ int solve_fp64(skr_context* c, const skr_matrix* M, int s, const T* B, T* X, boo
         return SKR_BREAKDOWN;
     }
     e.pc_on = e.pc != nullptr;
-    InnerStats st = iterate<T>(c, e, m, method, o.tol, o.maxit, o.check_every, o.use_graph != 0,
-                               fnv(&e.pc, sizeof(e.pc), fnv(&ar, sizeof(ar), 0)));
+    InnerStats st = small_eligible<T>(c, e, method, o)
+                        ? iterate_small<T>(c, e, method, o.tol, o.maxit, rhs, D)
+                        : iterate<T>(c, e, m, method, o.tol, o.maxit, o.check_every, o.use_graph != 0,
+                                     fnv(&e.pc, sizeof(e.pc), fnv(&ar, sizeof(ar), 0)));
     e.pc_on = false;
     if (e.pc) {   // the method solved A M^-1 D = Q: the correction is M^-1 D
         prec_apply(e, s, D, e.pc_tmp, false, nullptr);
@@ -887,6 +962,7 @@ void skr_opts_default(skr_opts* o) {
     o->precond = SKR_PRECOND_NONE;
     o->check_every = 16;
     o->use_graph = 1;
+    o->fused_small = 1;
 }
 
 int skr_context_create(int device, void* hip_stream, skr_context** out) {
@@ -914,6 +990,8 @@ int skr_context_create(int device, void* hip_stream, skr_context** out) {
     }
     // the allocation-free entry point's scratch on this device (once per device;
     // a failed lookup only disables that entry point, which then reports it)
+    if (hipDeviceGetAttribute(&c->lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess)
+        c->lds_max = 0;   // the single-workgroup small-system path stays off
     std::string why;
     c->scratch = scratch_addr(device, &why);
     if (!c->scratch) c->err = why;
