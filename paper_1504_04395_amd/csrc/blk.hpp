@@ -542,7 +542,7 @@ __device__ inline void set_bd(Ctl* c) { set_breakdown(c); }
 // 11 (ns + s(s+1)) 2^-53 tr(G); it is raised to 1e3 u tr(G) where that is
 // larger, so that the shifted Q1 (condition number <= (1e3 u)^{-1/2}) is still
 // orthonormal enough, in the stored precision, for the two passes after it.
-__global__ __launch_bounds__(kScalar) void k_qr_chol(Ctl* c, int slot, int pass, int n, int s, const c64* __restrict__ part2, int p2,
+__global__ __launch_bounds__(kCoefThreads) void k_qr_chol(Ctl* c, int slot, int pass, int n, int s, const c64* __restrict__ part2, int p2,
                           c64* __restrict__ mats, double u) {
     if (stopped(c)) return;
     if (pass == 3 && !c->qr_shift[slot]) return;
@@ -604,7 +604,7 @@ __global__ __launch_bounds__(kScalar) void k_qr_chol(Ctl* c, int slot, int pass,
 }
 
 // Bl-BiCG-rQ: G = V^^H W -> alpha = G^{-1} M, alpha^ = G^{-H} M^H, alpha C.
-__global__ __launch_bounds__(kScalar) void k_blrq_alpha(Ctl* c, int s, const c64* __restrict__ part2, int p2, c64* __restrict__ mats,
+__global__ __launch_bounds__(kCoefThreads) void k_blrq_alpha(Ctl* c, int s, const c64* __restrict__ part2, int p2, c64* __restrict__ mats,
                              c64* __restrict__ sc) {
     if (stopped(c)) return;
     extern __shared__ c64 dyn[];
@@ -641,7 +641,7 @@ __global__ __launch_bounds__(kScalar) void k_blrq_alpha(Ctl* c, int s, const c64
 
 // Bl-BiCG-rQ: M' = Q^'^H Q' -> C = S C, C^ = S^ C^, stopping test on ||C||_F,
 // beta = M^{-1} S^^H M', beta^ = M^{-H} S^H M'^H, M = M'.
-__global__ __launch_bounds__(kScalar) void k_blrq_beta(Ctl* c, double* hist, int s, const c64* __restrict__ part2, int p2,
+__global__ __launch_bounds__(kCoefThreads) void k_blrq_beta(Ctl* c, double* hist, int s, const c64* __restrict__ part2, int p2,
                             c64* __restrict__ mats) {
     if (stopped(c)) return;
     extern __shared__ c64 dyn[];
@@ -725,7 +725,7 @@ __global__ __launch_bounds__(kScalar) void k_bl_init(Ctl* c, double* hist, int s
 }
 
 // Bl-BiCGStab-rQ: G = R~^H W -> LU (kept), a = G^{-1} N (stored negated for S~ = Q - W a)
-__global__ __launch_bounds__(kScalar) void k_blst_a(Ctl* c, int s, const c64* __restrict__ part2, int p2, c64* __restrict__ mats,
+__global__ __launch_bounds__(kCoefThreads) void k_blst_a(Ctl* c, int s, const c64* __restrict__ part2, int p2, c64* __restrict__ mats,
                          c64* __restrict__ sc) {
     if (stopped(c)) return;
     extern __shared__ c64 dyn[];
@@ -751,7 +751,7 @@ __global__ __launch_bounds__(kScalar) void k_blst_a(Ctl* c, int s, const c64* __
 
 // Bl-BiCGStab-rQ: (T~^H S~, T~^H T~) -> omega = tr(T~^H S~ K) / tr(T~^H T~ K), K = C C^H;
 // a C and omega C for the X update.
-__global__ __launch_bounds__(kScalar) void k_blst_omega(Ctl* c, int s, const c64* __restrict__ part2, int p2, c64* __restrict__ mats,
+__global__ __launch_bounds__(kCoefThreads) void k_blst_omega(Ctl* c, int s, const c64* __restrict__ part2, int p2, c64* __restrict__ mats,
                              c64* __restrict__ sc) {
     if (stopped(c)) return;
     extern __shared__ c64 dyn[];
@@ -776,8 +776,8 @@ __global__ __launch_bounds__(kScalar) void k_blst_omega(Ctl* c, int s, const c64
         num = num + G1[e] * K[b * s + a];
         den = den + G2[e] * K[b * s + a];
     }
-    num = {wave_sum(num.x), wave_sum(num.y)};
-    den = {wave_sum(den.x), wave_sum(den.y)};
+    num = {wg_sum(num.x), wg_sum(num.y)};
+    den = {wg_sum(den.x), wg_sum(den.y)};
     if (threadIdx.x == 0) {
         if (bad_den(den)) {
             set_bd(c);
@@ -797,7 +797,7 @@ __global__ __launch_bounds__(kScalar) void k_blst_omega(Ctl* c, int s, const c64
 }
 
 // Bl-BiCGStab-rQ: N' = R~^H Q' -> C = Sigma C, stopping test, b = (1/omega) G^{-1} N', N = N'.
-__global__ __launch_bounds__(kScalar) void k_blst_b(Ctl* c, double* hist, int s, const c64* __restrict__ part2, int p2,
+__global__ __launch_bounds__(kCoefThreads) void k_blst_b(Ctl* c, double* hist, int s, const c64* __restrict__ part2, int p2,
                          c64* __restrict__ mats, c64* __restrict__ sc) {
     if (stopped(c)) return;
     extern __shared__ c64 dyn[];

@@ -299,17 +299,17 @@ void cholqr(Env<T>& e, int slot, const T* Z, T* Q, int mode, const T* Other) {
     const double u = sizeof(typename Tr<T>::R) == 4 ? 0x1p-24 : 0x1p-53;   // stored precision
     size_t lds4 = 4 * (size_t)ss * sizeof(c64);
     reduce2(e, ss);
-    k_qr_chol<<<1, kScalar, lds4, e.st>>>(e.ctl, slot, 1, e.n, s, e.part2, e.p2, e.mats, u);
+    k_qr_chol<<<1, kCoefThreads, lds4, e.st>>>(e.ctl, slot, 1, e.n, s, e.part2, e.p2, e.mats, u);
     SKR_LAUNCHED();
     // Gram of Q1 = Z S1^{-1}
     tri_pass<T, J>(e, slot, 0, 1, 0, TRI_G_OUT_OUT, Z, nullptr, nullptr);
     reduce2(e, ss);
-    k_qr_chol<<<1, kScalar, lds4, e.st>>>(e.ctl, slot, 2, e.n, s, e.part2, e.p2, e.mats, u);
+    k_qr_chol<<<1, kCoefThreads, lds4, e.st>>>(e.ctl, slot, 2, e.n, s, e.part2, e.p2, e.mats, u);
     SKR_LAUNCHED();
     // shifted case only: Gram of Q2 = Z S1^{-1} S2^{-1}
     tri_pass<T, J>(e, slot, 1, 2, 0, TRI_G_OUT_OUT, Z, nullptr, nullptr);
     reduce2(e, ss, slot);
-    k_qr_chol<<<1, kScalar, lds4, e.st>>>(e.ctl, slot, 3, e.n, s, e.part2, e.p2, e.mats, u);
+    k_qr_chol<<<1, kCoefThreads, lds4, e.st>>>(e.ctl, slot, 3, e.n, s, e.part2, e.p2, e.mats, u);
     SKR_LAUNCHED();
     // Q = Z S1^{-1} S2^{-1} [S3^{-1}]
     tri_pass<T, J>(e, slot, 0, 2, 1, mode | TRI_WRITE, Z, Q, Other);
@@ -561,13 +561,13 @@ Method<T> make_bl_bicg_rq(Env<T>& e, Arena& ar, T* rhs, T* x) {
         spmm_j<T, J>(e, e.A, lt, V, W, EpiGram<T, J>{Vh, e.part}, e.ctl);           // W = A V, G = V^^H W
         spmm_j<T, J>(e, e.AH, lt, Vh, Wh, EpiNone{}, e.ctl);                      // W^ = A^H V^
         reduce2(e, ss);
-        k_blrq_alpha<<<1, kScalar, 4 * (size_t)ss * sizeof(c64), e.st>>>(e.ctl, s, e.part2, e.p2, e.mats, e.sc);
+        k_blrq_alpha<<<1, kCoefThreads, 4 * (size_t)ss * sizeof(c64), e.st>>>(e.ctl, s, e.part2, e.p2, e.mats, e.sc);
         blrq_updz<T, J>(e, x, V, Q, W, Z);
         cholqr<T, J>(e, 0, Z, Q, 0, nullptr);                                     // Q' S = Q - W alpha
         axpm<T, J, true>(e, M_ALPHAH, 0, Qh, Wh, nullptr, Zh);
         cholqr<T, J>(e, 1, Zh, Qh, TRI_G_OUT_OTHER, Q);                           // Q^' S^, M' = Q^'^H Q'
         reduce2(e, ss);
-        k_blrq_beta<<<1, kScalar, 4 * (size_t)ss * sizeof(c64), e.st>>>(e.ctl, e.hist, s, e.part2, e.p2, e.mats);
+        k_blrq_beta<<<1, kCoefThreads, 4 * (size_t)ss * sizeof(c64), e.st>>>(e.ctl, e.hist, s, e.part2, e.p2, e.mats);
         axpm<T, J, false>(e, M_BETA, 0, Q, V, nullptr, V);
         axpm<T, J, false>(e, M_BETAH, 0, Qh, Vh, nullptr, Vh);
     };
@@ -602,15 +602,15 @@ Method<T> make_bl_bicgstab_rq(Env<T>& e, Arena& ar, T* rhs, T* x) {
     m.iter = [=, &e]() {
         spmm_j<T, J>(e, e.A, lt, U, W, EpiGram<T, J>{Rt, e.part}, e.ctl);           // W = A U, G = R~^H W
         reduce2(e, ss);
-        k_blst_a<<<1, kScalar, 4 * (size_t)ss * sizeof(c64), e.st>>>(e.ctl, s, e.part2, e.p2, e.mats, e.sc);
+        k_blst_a<<<1, kCoefThreads, 4 * (size_t)ss * sizeof(c64), e.st>>>(e.ctl, s, e.part2, e.p2, e.mats, e.sc);
         axpm<T, J, false>(e, M_TMP, 0, Q, W, nullptr, St);                         // S~ = Q - W a
         spmm_j<T, J>(e, e.A, lt, St, Tt, EpiGramOmega<T, J>{St, e.part}, e.ctl);    // T~ = A S~
         reduce2(e, 2 * ss);
-        k_blst_omega<<<1, kScalar, 4 * (size_t)ss * sizeof(c64), e.st>>>(e.ctl, s, e.part2, e.p2, e.mats, e.sc);
+        k_blst_omega<<<1, kCoefThreads, 4 * (size_t)ss * sizeof(c64), e.st>>>(e.ctl, s, e.part2, e.p2, e.mats, e.sc);
         blst_upd<T, J>(e, x, U, St, Tt, Z);
         cholqr<T, J>(e, 0, Z, Q, TRI_G_OTHER_OUT, Rt);                            // Q' Sigma = Z, N' = R~^H Q'
         reduce2(e, ss);
-        k_blst_b<<<1, kScalar, 4 * (size_t)ss * sizeof(c64), e.st>>>(e.ctl, e.hist, s, e.part2, e.p2, e.mats, e.sc);
+        k_blst_b<<<1, kCoefThreads, 4 * (size_t)ss * sizeof(c64), e.st>>>(e.ctl, e.hist, s, e.part2, e.p2, e.mats, e.sc);
         axpm<T, J, false>(e, M_B, SC_GAMMA, Q, U, W, U);                           // U = Q + (U - omega W) b
     };
     return m;
@@ -703,7 +703,7 @@ Method<T> make_bl_bicgstab(Env<T>& e, Arena& ar, T* rhs, T* x) {
     m.iter = [=, &e]() {
         spmm_j<T, J>(e, e.A, lt, P, V, EpiGram<T, J>{Rt, e.part}, e.ctl);           // V = A P, G = R~^H V
         reduce2(e, ss);
-        k_blst_a<<<1, kScalar, lds4, e.st>>>(e.ctl, s, e.part2, e.p2, e.mats, e.sc); // alpha = G^{-1} N
+        k_blst_a<<<1, kCoefThreads, lds4, e.st>>>(e.ctl, s, e.part2, e.p2, e.mats, e.sc); // alpha = G^{-1} N
         SKR_LAUNCHED();
         axpm<T, J, false>(e, M_TMP, 0, R, V, nullptr, S);                           // S = R - V alpha
         spmm(e, e.A, e.ly, S, Tm, EpiTraceOmega<T>{S, e.part}, e.ctl);              // T = A S

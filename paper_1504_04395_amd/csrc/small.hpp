@@ -3,10 +3,12 @@
 // pivot breakdown test, solves with G and with G^H, upper Cholesky factors
 // (G = S^H S), triangular inverses and small products.  Matrices are row-major
 // complex doubles; real problems carry zero imaginary parts, which every routine
-// here keeps exactly zero.  All routines are called by the whole workgroup, which
-// is one wavefront (64 threads): reductions across it use lane shuffles, and
-// the steps of a factorisation or substitution are parallel over the matrix
-// entries they update, with a barrier between steps.
+// here keeps exactly zero.  All routines are called by the whole workgroup: one
+// wavefront, or kCoefThreads threads for the per-iteration coefficient kernels
+// of the block methods, whose elimination steps then update one entry per
+// thread instead of four.  The steps of a factorisation or substitution are
+// parallel over the matrix entries they update, with a barrier between steps;
+// reductions take a butterfly within each wave and the waves in order.
 #pragma once
 
 #include "common.hpp"
@@ -44,6 +46,8 @@ __device__ inline void sm_gemm(c64* C, const c64* A, int ta, const c64* B, int t
     __syncthreads();
 }
 
+constexpr int kCoefThreads = 256;   // workgroup of the block methods' coefficient kernels
+
 __device__ inline double wave_max(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
@@ -51,12 +55,49 @@ __device__ inline double wave_max(double v) {
 }
 __device__ inline int wave_all(int ok) { return __all(ok); }
 
-// ||A||_F^2 over `count` entries (fixed order: strided per lane, butterfly).
+// Workgroup reductions for up to kCoefThreads threads (one wave: the wave's own
+// result).  Every thread receives the result; the waves are combined in order.
+__device__ inline double wg_sum(double v) {
+    v = wave_sum(v);
+    if (blockDim.x <= 64) return v;
+    __shared__ double r[kCoefThreads / 64];
+    __syncthreads();   // an earlier call's readers are done
+    if ((threadIdx.x & 63) == 0) r[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = r[0];
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) t += r[i];
+    return t;
+}
+__device__ inline double wg_max(double v) {
+    v = wave_max(v);
+    if (blockDim.x <= 64) return v;
+    __shared__ double r[kCoefThreads / 64];
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) r[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = r[0];
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) t = fmax(t, r[i]);
+    return t;
+}
+__device__ inline int wg_all(int ok) {
+    ok = __all(ok);
+    if (blockDim.x <= 64) return ok;
+    __shared__ int r[kCoefThreads / 64];
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) r[threadIdx.x >> 6] = ok;
+    __syncthreads();
+    int t = 1;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t &= r[i];
+    return t;
+}
+
+// ||A||_F^2 over `count` entries (fixed order: strided per thread, butterfly,
+// waves in order).
 __device__ inline double sm_frob2(const c64* A, int count, double* red /* unused */) {
     (void)red;
     double t = 0.0;
     for (int e = threadIdx.x; e < count; e += blockDim.x) t += abs2(A[e]);
-    return wave_sum(t);
+    return wg_sum(t);
 }
 
 // Work split of an update over the rows of an s x m array: thread t owns
@@ -91,23 +132,26 @@ __device__ inline int sm_lu(c64* __restrict__ A, int* __restrict__ piv, int s, i
     const int t = threadIdx.x;
     const Split sp = split_cols(s);
     for (int k = 0; k < s; ++k) {
-        double v = -1.0;
-        int idx = k;
-        if (t >= k && t < s) {
-            v = cabs1(A[t * s + k]);
-            idx = t;
-        }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            const double v2 = __shfl_xor(v, off, 64);
-            const int i2 = __shfl_xor(idx, off, 64);
-            if (v2 > v || (v2 == v && i2 < idx)) {
-                v = v2;
-                idx = i2;
+        if (t < 64) {   // the first wave searches the column (rows k..s-1, s <= 64)
+            double v = -1.0;
+            int idx = k;
+            if (t >= k && t < s) {
+                v = cabs1(A[t * s + k]);
+                idx = t;
             }
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                const double v2 = __shfl_xor(v, off, 64);
+                const int i2 = __shfl_xor(idx, off, 64);
+                if (v2 > v || (v2 == v && i2 < idx)) {
+                    v = v2;
+                    idx = i2;
+                }
+            }
+            if (t == 0) piv[k] = idx;
         }
-        const int p = idx;
-        if (t == 0) piv[k] = p;
+        __syncthreads();
+        const int p = piv[k];
         if (p != k) {
             for (int j = t; j < s; j += blockDim.x) {
                 c64 x = A[k * s + j];
@@ -136,11 +180,11 @@ __device__ inline int sm_lu(c64* __restrict__ A, int* __restrict__ piv, int s, i
         if (!cfinite(u)) fin = 0;
         if (j >= i) umax = fmax(umax, cabs(u));
     }
-    umax = wave_max(umax);
+    umax = wg_max(umax);
     int ok = fin && umax > 0.0;
     for (int k = t; k < s; k += blockDim.x)
         if (!(cabs(A[k * s + k]) > s * 0x1p-52 * umax)) ok = 0;
-    return wave_all(ok);
+    return wg_all(ok);
 }
 
 // B := G^{-1} B for B s x m (row-major, leading dimension m), G = P^T L U.
