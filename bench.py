@@ -328,7 +328,7 @@ def perturbed_counts(pkg, inputs, grid, seeds, maxit):
 
 def config1_latency(pkg, inputs, reps=7):
     """The small 2D workload (32 x 32 grid, n = 1024, s = 4, FP64): Gl-BiCG and
-    eGl-BiCG to 1e-8 on the single-workgroup path (every iteration in one
+    eGl-BiCG (and Gl-BiCGStab) to 1e-8 on the single-workgroup path (every iteration in one
     launch, the default for this size) and on the general schedule with the
     iteration captured in a hipGraph and launched eagerly; the median solve
     time of `reps`, microseconds per iteration, and the oracle's full solve in
@@ -342,7 +342,7 @@ def config1_latency(pkg, inputs, reps=7):
     B = torch.from_numpy(prob.B).cuda()
     X = torch.zeros_like(B)
     rows = {}
-    for m in ("gl_bicg", "egl_bicg"):
+    for m in ("gl_bicg", "egl_bicg", "gl_bicgstab"):   # the workload's two methods, and the third fused one
         r = {}
         for mode, fused, graph in (("fused", True, True), ("graph", False, True), ("eager", False, False)):
             ts = []

@@ -106,9 +106,9 @@ typedef struct {
                              * M = L U from skr_matrix_ilu0 and returns
                              * X = X0 + M^-1 D; residuals stay those of A X = B.
                              * FP64, non-adjoint solves only                 [NONE]  */
-    int32_t fused_small;    /* FP64 Gl-BiCG / eGl-BiCG on at most 1024 rows with
-                             * CSR storage, no preconditioner and s <= 4 (real)
-                             * or s <= 2 (complex): run every iteration in one
+    int32_t fused_small;    /* FP64 Gl-BiCG / eGl-BiCG / Gl-BiCGStab on at most
+                             * 1024 rows with CSR storage, no preconditioner and
+                             * s <= 4 (real) or s <= 2 (complex): run every iteration in one
                              * single-workgroup launch instead of the
                              * multi-kernel schedule.  Same iteration, stopping
                              * rule and history; check_every and use_graph do

@@ -318,7 +318,8 @@ def solve(ctx: Context, A: Matrix, B, method: str, X=None, x0_zero: bool = False
     guess / output array of the same kind (a new one is created if None);
     with x0_zero the contents of X are ignored (X0 = 0).  precond='ilu0':
     right ILU(0) preconditioning (A.ilu0() first).  fused_small=False keeps
-    small Gl-BiCG / eGl-BiCG systems on the general multi-kernel schedule.
+    small Gl-BiCG / eGl-BiCG / Gl-BiCGStab systems on the general multi-kernel
+    schedule.
     Returns (X, SolveInfo)."""
     lib = load_library()
     _check_block(B, A.n, A.dtype, "B")

@@ -568,27 +568,35 @@ InnerStats iterate(skr_context* c, Env<T>& e, Method<T>& m, int method, double t
     return inner_stats(c, e, m.mv_per_iter);
 }
 
-// Dynamic LDS of the single-workgroup Gl-BiCG / eGl-BiCG kernel: P (n x s),
-// then P^ (n x s) or p^ (n).
+// Dynamic LDS of the single-workgroup kernels: P (n x s), then P^ (n x s) or
+// p^ (n) for Gl-BiCG / eGl-BiCG; one n x s block (P, then S) for Gl-BiCGStab.
 template <class T>
-size_t small_lds_bytes(int n, int s, bool econ) {
-    return sizeof(T) * ((size_t)n * s + (econ ? (size_t)n : (size_t)n * s));
+size_t small_lds_bytes(int n, int s, int method) {
+    const size_t blk = (size_t)n * s;
+    if (method == SKR_GL_BICGSTAB) return sizeof(T) * blk;
+    return sizeof(T) * (blk + (method == SKR_EGL_BICG ? (size_t)n : blk));
 }
 
-// A system the single-workgroup kernel takes: Gl-BiCG or eGl-BiCG, CSR
-// operands, no preconditioner, n <= 1024 rows, s within the register budget
-// and both LDS blocks within one workgroup's LDS (with 1 KiB left for the
-// kernel's reduction slots).
+// A system the single-workgroup kernels take: Gl-BiCG, eGl-BiCG or
+// Gl-BiCGStab, CSR operands, no preconditioner, n <= 1024 rows, s within the
+// register budget and the LDS blocks within one workgroup's LDS (with 1 KiB left
+// for the kernels' reduction slots).
 template <class T>
 bool small_eligible(const skr_context* c, const Env<T>& e, int method, const skr_opts& o) {
-    if (!o.fused_small || (method != SKR_GL_BICG && method != SKR_EGL_BICG)) return false;
+    if (!o.fused_small || (method != SKR_GL_BICG && method != SKR_EGL_BICG && method != SKR_GL_BICGSTAB))
+        return false;
     if (e.n < 1 || e.n > kSmallMaxRows || e.s > SmallMaxS<T>::value || e.A.sell || e.AH.sell || e.pc) return false;
-    return small_lds_bytes<T>(e.n, e.s, method == SKR_EGL_BICG) + 1024 <= (size_t)c->lds_max;
+    return small_lds_bytes<T>(e.n, e.s, method) + 1024 <= (size_t)c->lds_max;
 }
 
 template <class T, int S>
-void launch_small(Env<T>& e, bool econ, size_t lds, const T* rhs, T* D) {
-    if (econ) {
+void launch_small(Env<T>& e, int method, size_t lds, const T* rhs, T* D) {
+    const bool econ = method == SKR_EGL_BICG;
+    if (method == SKR_GL_BICGSTAB) {
+        SKR_HIP(hipFuncSetAttribute((const void*)k_small_bicgstab<T, S>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)lds));
+        k_small_bicgstab<T, S><<<1, kSmallThreads, lds, e.st>>>(e.ctl, e.hist, e.A.csr, rhs, D);
+    } else if (econ) {
         SKR_HIP(hipFuncSetAttribute((const void*)k_small_bicg<T, true, S>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         k_small_bicg<T, true, S><<<1, kSmallThreads, lds, e.st>>>(e.ctl, e.hist, e.A.csr, e.AH.csr, rhs, D);
@@ -599,8 +607,9 @@ void launch_small(Env<T>& e, bool econ, size_t lds, const T* rhs, T* D) {
     }
 }
 
-// Run Gl-BiCG or eGl-BiCG on A D = rhs in one launch (every iteration inside
-// one workgroup); same stopping rule, breakdown rules and history as iterate.
+// Run Gl-BiCG, eGl-BiCG or Gl-BiCGStab on A D = rhs in one launch (every
+// iteration inside one workgroup); same stopping rule, breakdown rules and
+// history as iterate.
 template <class T>
 InnerStats iterate_small(skr_context* c, Env<T>& e, int method, double tol, int maxit, const T* rhs, T* D) {
     Ctl* h = c->hin;
@@ -610,27 +619,26 @@ InnerStats iterate_small(skr_context* c, Env<T>& e, int method, double tol, int 
     h->maxit = maxit;
     h->tol = tol;
     SKR_HIP(hipMemcpyAsync(e.ctl, h, sizeof(Ctl), hipMemcpyHostToDevice, e.st));
-    const bool econ = method == SKR_EGL_BICG;
-    const size_t lds = small_lds_bytes<T>(e.n, e.s, econ);
+    const size_t lds = small_lds_bytes<T>(e.n, e.s, method);
     if constexpr (Tr<T>::cplx) {
         switch (e.s) {
-            case 1: launch_small<T, 1>(e, econ, lds, rhs, D); break;
-            case 2: launch_small<T, 2>(e, econ, lds, rhs, D); break;
+            case 1: launch_small<T, 1>(e, method, lds, rhs, D); break;
+            case 2: launch_small<T, 2>(e, method, lds, rhs, D); break;
             default: throw Unsupported{"single-workgroup path: block too wide"};
         }
     } else {
         switch (e.s) {
-            case 1: launch_small<T, 1>(e, econ, lds, rhs, D); break;
-            case 2: launch_small<T, 2>(e, econ, lds, rhs, D); break;
-            case 3: launch_small<T, 3>(e, econ, lds, rhs, D); break;
-            case 4: launch_small<T, 4>(e, econ, lds, rhs, D); break;
+            case 1: launch_small<T, 1>(e, method, lds, rhs, D); break;
+            case 2: launch_small<T, 2>(e, method, lds, rhs, D); break;
+            case 3: launch_small<T, 3>(e, method, lds, rhs, D); break;
+            case 4: launch_small<T, 4>(e, method, lds, rhs, D); break;
             default: throw Unsupported{"single-workgroup path: block too wide"};
         }
     }
     SKR_LAUNCHED();
     SKR_HIP(hipMemcpyAsync(c->hout, e.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, e.st));
     SKR_HIP(hipStreamSynchronize(e.st));
-    return inner_stats(c, e, econ ? (long long)e.s + 1 : 2LL * e.s);
+    return inner_stats(c, e, method == SKR_EGL_BICG ? (long long)e.s + 1 : 2LL * e.s);
 }
 
 // True residual: part = (||B - A X||^2, ||B||^2) -> host

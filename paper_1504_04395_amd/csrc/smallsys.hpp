@@ -1,5 +1,5 @@
-// Gl-BiCG (Algorithm 2) and eGl-BiCG (Algorithm 4) for small systems, every
-// iteration in one kernel launch on one workgroup.
+// Gl-BiCG (Algorithm 2), eGl-BiCG (Algorithm 4) and Gl-BiCGStab (Section 4)
+// for small systems, every iteration in one kernel launch on one workgroup.
 //
 // With n <= 1024 rows, one workgroup of 1024 threads holds the whole block
 // system: thread i keeps row i of X, R, P and of the shadow R^, P^ (or the
@@ -291,6 +291,151 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_bicg(Ctl* ctl, double* 
 #pragma unroll
         for (int c = 0; c < SM; ++c)
             x[(size_t)i * s + c] = X[c];
+    }
+}
+
+// Gl-BiCGStab (the global BiCGStab of Section 4) on the same single-workgroup
+// layout: thread i keeps row i of X, R, R~ (the shadow R0), P, V = A P, S and
+// T = A S.  The two products gather from one LDS block, P first and then S.
+// Five barriers per iteration: after each LDS write, and in the three workgroup
+// sums (sigma = tr(R~^H V); tr(T^H S) with tr(T^H T); ||R||^2 with rho').
+template <class T, int S>
+__global__ __launch_bounds__(kSmallThreads) void k_small_bicgstab(Ctl* ctl, double* hist, CsrOp<T> A,
+                                                                  const T* __restrict__ rhs, T* __restrict__ x) {
+    constexpr int s = S;
+    constexpr int NW = kSmallThreads / 64;
+    constexpr int KB = SmallBatch<T>::value;
+    static_assert(NW == 16, "the workgroup sums take one 16-lane row of wave sums");
+    using V = Val<T>;
+    extern __shared__ c64 dyn[];
+    T* Bl = reinterpret_cast<T*>(dyn);   // P, then S, of every row
+    __shared__ V red_sig[NW], red_num[NW], red_rho[NW];
+    __shared__ double red_den[NW], red_nrm[NW];
+    const int n = A.n;
+    const int i = threadIdx.x;
+    const bool row = i < n;
+    const double tol = ctl->tol;
+    const int maxit = ctl->maxit;
+    const int a0 = row ? A.rp[i] : 0, a1 = row ? A.rp[i + 1] : 0;
+    // row i of A times the LDS block (entries in ascending order, KB at a time)
+    auto product = [&](T (&Y)[S]) {
+        int ca[KB];
+        T va[KB];
+#pragma unroll
+        for (int c = 0; c < S; ++c) Y[c] = zero<T>();
+        small_fetch(A, a0, a1, ca, va);
+        for (int k = a0;;) {
+#pragma unroll
+            for (int u = 0; u < KB; ++u) {
+                if (k + u < a1) {
+                    const T* pr = Bl + (size_t)ca[u] * s;
+#pragma unroll
+                    for (int c = 0; c < S; ++c) Y[c] = fma_(va[u], pr[c], Y[c]);
+                }
+            }
+            k += KB;
+            if (k >= a1) break;
+            small_fetch(A, k, a1, ca, va);
+        }
+    };
+    T X[S], R[S], Rt[S], P[S];
+#pragma unroll
+    for (int c = 0; c < S; ++c) {
+        X[c] = zero<T>();
+        R[c] = row ? rhs[(size_t)i * s + c] : zero<T>();
+        Rt[c] = R[c];
+        P[c] = R[c];
+    }
+    double nr = 0.0;
+    V rho = vzero<V>();
+#pragma unroll
+    for (int c = 0; c < S; ++c) {
+        nr = snrm(R[c], nr);
+        rho = sdot(Rt[c], R[c], rho);
+    }
+    small_allreduce2(nr, rho, red_nrm, red_rho);
+    const double nr0 = sqrt(nr);
+    bool go = nr0 > 0.0 && isfinite(nr0) && maxit > 0;
+    if (threadIdx.x == 0) {
+        ctl->nr0 = nr0;
+        ctl->res = nr0;
+        ctl->iter = 0;
+        ctl->bd_iter = -1;
+        hist[0] = 1.0;
+        ctl->status = !(nr0 > 0.0) ? ST_OK : (!isfinite(nr0) ? ST_BREAKDOWN : ST_RUNNING);
+        ctl->done = go ? 0 : 1;
+    }
+    int it = 0;
+    while (go) {
+        if (row) {
+#pragma unroll
+            for (int c = 0; c < S; ++c) Bl[(size_t)i * s + c] = P[c];
+        }
+        __syncthreads();
+        T Vr[S];
+        product(Vr);   // V = A P
+        V sg = vzero<V>();
+#pragma unroll
+        for (int c = 0; c < S; ++c) sg = sdot(Rt[c], Vr[c], sg);
+        const c64 sigma = sc64(small_allreduce(sg, red_sig));   // also orders the reads of P before the writes of S
+        if (bad_den(sigma)) {
+            if (threadIdx.x == 0) set_breakdown(ctl);
+            break;
+        }
+        const c64 alpha = cdiv(sc64(rho), sigma);
+        const T a = down<T>(alpha), ma = down<T>(-alpha);
+        T Sr[S];
+#pragma unroll
+        for (int c = 0; c < S; ++c) Sr[c] = fma_(ma, Vr[c], R[c]);
+        if (row) {
+#pragma unroll
+            for (int c = 0; c < S; ++c) Bl[(size_t)i * s + c] = Sr[c];
+        }
+        __syncthreads();
+        T Tr[S];
+        product(Tr);   // T = A S
+        V num = vzero<V>();
+        double den = 0.0;
+#pragma unroll
+        for (int c = 0; c < S; ++c) {
+            num = sdot(Tr[c], Sr[c], num);
+            den = snrm(Tr[c], den);
+        }
+        small_allreduce2(den, num, red_den, red_num);   // orders the reads of S before the next writes
+        if (bad_den(c64{den, 0.0})) {
+            if (threadIdx.x == 0) set_breakdown(ctl);
+            break;
+        }
+        const c64 omega = cdiv(sc64(num), c64{den, 0.0});
+        const T w = down<T>(omega), mw = down<T>(-omega);
+        nr = 0.0;
+        V rhon = vzero<V>();
+#pragma unroll
+        for (int c = 0; c < S; ++c) {
+            X[c] = fma_(w, Sr[c], fma_(a, P[c], X[c]));
+            R[c] = fma_(mw, Tr[c], Sr[c]);
+            nr = snrm(R[c], nr);
+            rhon = sdot(Rt[c], R[c], rhon);
+        }
+        small_allreduce2(nr, rhon, red_nrm, red_rho);
+        ++it;
+        const double res = sqrt(nr);
+        go = !(res <= tol * nr0) && isfinite(res) && it < maxit;
+        if (threadIdx.x == 0) (void)end_of_iteration(ctl, hist, nr);
+        if (go && (bad_den(sc64(rho)) || bad_den(omega))) {
+            if (threadIdx.x == 0) set_breakdown(ctl);
+            go = false;
+        }
+        if (!go) break;
+        const c64 beta = cdiv(sc64(rhon), sc64(rho)) * cdiv(alpha, omega);
+        rho = rhon;
+        const T b = down<T>(beta);
+#pragma unroll
+        for (int c = 0; c < S; ++c) P[c] = fma_(b, fma_(mw, Vr[c], P[c]), R[c]);
+    }
+    if (row) {
+#pragma unroll
+        for (int c = 0; c < S; ++c) x[(size_t)i * s + c] = X[c];
     }
 }
 

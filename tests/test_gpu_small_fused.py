@@ -1,4 +1,4 @@
-"""The single-workgroup Gl-BiCG / eGl-BiCG path for small systems (n <= 1024,
+"""The single-workgroup Gl-BiCG / eGl-BiCG / Gl-BiCGStab path for small systems (n <= 1024,
 s <= 4 real or s <= 2 complex, CSR, no preconditioner), through the C ABI:
 against the oracle at a fixed iteration count and at convergence, and against
 the general multi-kernel schedule (fused_small=False) on the same inputs."""
@@ -58,7 +58,10 @@ SHAPES = [("convdiff", 1024, s) for s in (1, 2, 3, 4)] + \
           ("powerlaw", 1000, 1), ("powerlaw", 1000, 2), ("powerlaw", 517, 2)]
 
 
-@pytest.mark.parametrize("method", ["gl_bicg", "egl_bicg"])
+FUSED = ["gl_bicg", "egl_bicg", "gl_bicgstab"]
+
+
+@pytest.mark.parametrize("method", FUSED)
 @pytest.mark.parametrize("kind,n,s", SHAPES)
 def test_fixed_iterations_match_oracle(pkg, ctx, kind, n, s, method):
     """Eight iterations on both sides: iterates and history agree to 1e-10."""
@@ -75,7 +78,7 @@ def test_fixed_iterations_match_oracle(pkg, ctx, kind, n, s, method):
     np.testing.assert_allclose(info.history, ref.history, rtol=1e-10, atol=0)
 
 
-@pytest.mark.parametrize("method", ["gl_bicg", "egl_bicg"])
+@pytest.mark.parametrize("method", FUSED)
 @pytest.mark.parametrize("kind,n,s", SHAPES)
 def test_converged_matches_general_schedule(pkg, ctx, kind, n, s, method):
     """To 1e-12: the fused path and the general schedule reach the same status,
@@ -100,18 +103,25 @@ def test_converged_matches_general_schedule(pkg, ctx, kind, n, s, method):
     assert i1.rel_res_true < 1e-11
 
 
-@pytest.mark.parametrize("method", ["gl_bicg", "egl_bicg"])
+@pytest.mark.parametrize("method", FUSED)
 def test_one_row_and_size_limits(pkg, ctx, method):
-    """n = 1 (one iteration solves it; without the QR preprocessing, which needs
-    s <= n columns of full rank and reports a breakdown before the first
-    iteration otherwise), and n = 1024 / 1025 on either side of the
-    single-workgroup limit (the larger one runs the general schedule)."""
+    """n = 1 (without the QR preprocessing, which needs s <= n columns of full
+    rank and reports a breakdown before the first iteration otherwise): one
+    BiCG iteration solves it; BiCGStab's half step solves it too, and the zero
+    T = A S then breaks the omega quotient, as in the oracle.  And n = 1024 /
+    1025 on either side of the single-workgroup limit (the larger one runs the
+    general schedule)."""
     C1 = I.CSR(1, np.array([0, 1], dtype=np.int64), np.array([0], dtype=np.int32), np.array([4.0]))
     B1 = np.array([[2.0, -1.0, 0.5, 3.0]])
     A = pkg.Matrix.from_csr(ctx, C1)
     X, info = pkg.solve(ctx, A, B1, method, tol=1e-12, preprocess_qr=False)
-    assert info.status_name == "ok" and info.iterations == 1
-    np.testing.assert_allclose(X, B1 / 4.0, rtol=1e-15)
+    ref = O.solve(C1, B1, method, tol=1e-12, preprocess=False)
+    assert info.status == ref.status and info.iterations == ref.iterations
+    if method == "gl_bicgstab":
+        assert info.status_name == "breakdown" and info.breakdown_iter == 0 and np.all(X == 0)
+    else:
+        assert info.status_name == "ok" and info.iterations == 1
+        np.testing.assert_allclose(X, B1 / 4.0, rtol=1e-15)
     X, info = pkg.solve(ctx, A, B1, method, tol=1e-12)
     assert info.status_name == "breakdown" and info.iterations == 0
     A.close()
@@ -132,7 +142,7 @@ def test_zero_iterations_and_zero_rhs(pkg, ctx):
     C = I.convdiff2d(16)
     B = I.gaussian_block(C.n, 2, seed=3)
     A = pkg.Matrix.from_csr(ctx, C)
-    for method in ("gl_bicg", "egl_bicg"):
+    for method in FUSED:
         X, info = pkg.solve(ctx, A, B, method, maxit=0)
         assert info.status_name == "not_converged" and info.iterations == 0 and np.all(X == 0)
         X, info = pkg.solve(ctx, A, np.zeros_like(B), method, preprocess_qr=False)
@@ -147,7 +157,7 @@ def test_warm_start_and_adjoint(pkg, ctx):
     B = I.gaussian_block(C.n, 2, seed=4, complex_=True)
     X0 = I.gaussian_block(C.n, 2, seed=5, complex_=True)
     A = pkg.Matrix.from_csr(ctx, C)
-    for method in ("gl_bicg", "egl_bicg"):
+    for method in FUSED:
         ref = O.solve(C, B, method, X0=X0, tol=0.0, maxit=7)
         X, info = pkg.solve(ctx, A, B, method, X=X0.copy(), tol=0.0, maxit=7)
         assert info.iterations == 7 and _rel(X, ref.X) < 1e-10
@@ -166,7 +176,7 @@ def test_repeatable_bit_for_bit(pkg, ctx):
     C = I.convdiff2d(32)
     B = I.gaussian_block(C.n, 4, seed=2)
     A = pkg.Matrix.from_csr(ctx, C)
-    for method in ("gl_bicg", "egl_bicg"):
+    for method in FUSED:
         X1, i1 = pkg.solve(ctx, A, B, method, tol=1e-10)
         X2, i2 = pkg.solve(ctx, A, B, method, tol=1e-10)
         assert i1.iterations == i2.iterations and np.array_equal(X1, X2)
