@@ -267,12 +267,13 @@ def paper_table2(pkg, ctx, inputs, reps=3, examples=(1, 2, 3), preconds=(None, "
     return rows
 
 
-def config_solves(pkg, ctx, inputs, k, methods, precision, fmt, reps, inner_tol=1e-4, max_outer=20):
+def config_solves(pkg, ctx, inputs, k, methods, precision, fmt, reps, inner_tol=1e-4, max_outer=20, precond=None):
     """Solve workload k of inputs.config (full size) with each method to 1e-8
     (at most 3000 iterations); the best of `reps` timed solves per method.  With
     FP32 inner solves, `inner_tol` and `max_outer` set the refinement, and the
     record carries the true relative residual before each outer step and
-    after the last."""
+    after the last.  precond='ilu0': right ILU(0) (FP64), with its set-up time
+    (host factorisation and level schedules) in the record."""
     import numpy as np
     import torch
     prob = inputs.config(k, "full")
@@ -281,6 +282,15 @@ def config_solves(pkg, ctx, inputs, k, methods, precision, fmt, reps, inner_tol=
     B = torch.from_numpy(np.ascontiguousarray(prob.B)).cuda()
     X = torch.zeros_like(B)
     kw = {} if precision == "fp64" else dict(precision=precision, inner_tol=inner_tol, max_outer=max_outer)
+    setup_s = None
+    if precond:
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        A.ilu0()
+        torch.cuda.synchronize()
+        setup_s = round(time.perf_counter() - t, 4)
+        log(f"ILU(0) set-up {setup_s * 1e3:.1f} ms")
+        kw["precond"] = precond
     rows = []
     for m in methods or prob.methods:
         best = None
@@ -294,6 +304,8 @@ def config_solves(pkg, ctx, inputs, k, methods, precision, fmt, reps, inner_tol=
         row = {"workload": prob.name, "format": fmt, "precision": precision, "method": m,
                "status": info.status_name, "iterations": info.iterations,
                "outer": info.outer_iterations, "rel_res_true": info.rel_res_true, "seconds": round(best, 4)}
+        if precond:
+            row.update(precond=precond, precond_setup_s=setup_s)
         if precision != "fp64":
             row.update(inner_tol=inner_tol, max_outer=max_outer, outer_redone_in_fp64=info.fp64_outer_iterations,
                        outer_history=[float(f"{h:.3e}") for h in info.history])
@@ -486,7 +498,8 @@ def main():
                     help="instead of the benchmark: Examples 1-3 of Section 5.1 at full size with "
                          "every method (tol 1e-10, 500 iterations), beside the paper's Table 2")
     ap.add_argument("--examples", default="1,2,3", help="with --paper-table2: which examples")
-    ap.add_argument("--precond", default="none,ilu0", help="with --paper-table2: none, ilu0 or both")
+    ap.add_argument("--precond", default="none,ilu0",
+                    help="with --paper-table2: none, ilu0 or both; with --config: ilu0 preconditions the solves")
     ap.add_argument("--methods", default="", help="with --paper-table2 or --config: comma-separated subset")
     ap.add_argument("--reps", type=int, default=3, help="with --paper-table2 or --config: solves per entry "
                                                           "(best is kept)")
@@ -528,7 +541,8 @@ def main():
     if args.config and not args.spmm_only:
         ctx = pkg.Context(0)
         rows = config_solves(pkg, ctx, inputs, args.config, tuple(m for m in args.methods.split(",") if m),
-                             args.precision, args.format, args.reps, args.inner_tol, args.max_outer)
+                             args.precision, args.format, args.reps, args.inner_tol, args.max_outer,
+                             "ilu0" if args.precond == "ilu0" else None)
         print(json.dumps({"config_solves": rows}), flush=True)
         ctx.close()
         return
