@@ -514,36 +514,72 @@ __global__ __launch_bounds__(kBlock) void k_spmm_csr8(const Ctl* ctl, CsrOp<T> A
     epi_finish<Epi, 1>(epi, st, blockIdx.x, s);
 }
 
-// Single vector (s = 1): y = A x with 8 lanes per row.  Lane e of a row's group
-// takes entries k0 + e, k0 + e + 8, ... and the 8 partial sums are added by a
-// butterfly inside the group, in FP64 whatever the storage precision.  Same
-// per-XCD row sweep as k_spmm_csr.
 __device__ inline double shfl_xor_v(double v, int off) { return __shfl_xor(v, off, 64); }
 __device__ inline float shfl_xor_v(float v, int off) { return __shfl_xor(v, off, 64); }
 __device__ inline c64 shfl_xor_v(c64 v, int off) { return {__shfl_xor(v.x, off, 64), __shfl_xor(v.y, off, 64)}; }
 __device__ inline c32 shfl_xor_v(c32 v, int off) { return {__shfl_xor(v.x, off, 64), __shfl_xor(v.y, off, 64)}; }
 
+
+// Single vector (s = 1): y = A x with 8 lanes per row.  Lane e of a row's group
+// takes entries k0 + e, k0 + e + 8, ... and the 8 partial sums are added by a
+// butterfly inside the group, in FP64 whatever the storage precision.  Same
+// per-XCD row sweep as k_spmm_csr, software-pipelined like k_spmm_csr8: the
+// next pass's row pointers (loaded unconditionally, clamped) and first entries
+// are in flight while this pass's x gathers are; the order of the sums is that
+// of the plain sweep.  (Two rows per 8-lane group and pass were measured too:
+// no faster.)
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_spmv_csr(const Ctl* ctl, CsrOp<T> A, int rows_per_xcd,
                                                       const T* __restrict__ x, T* __restrict__ y) {
     if (stopped(ctl)) return;
+    using W = Val<T>;   // double or c64
     const int sub = threadIdx.x & 7;
     const int grp = threadIdx.x >> 3;                     // 32 rows per workgroup pass
     const int xcd = blockIdx.x & 7, q = blockIdx.x >> 3, nq = gridDim.x >> 3;
     const int r0 = xcd * rows_per_xcd;
     const int r1 = min(A.n, r0 + rows_per_xcd);
-    for (int base = r0 + q * 32; base < r1; base += nq * 32) {
-        const int i = base + grp;
-        const bool valid = i < r1;                         // uniform inside the 8-lane group
-        const int k0 = valid ? A.rp[i] : 0;
-        const int k1 = valid ? A.rp[i + 1] : 0;
-        using W = Val<T>;   // double or c64
-        W acc = vzero<W>();
-        for (int k = k0 + sub; k < k1; k += 8) acc = vfma(vup(A.va[k]), vup(x[A.ci[k]]), acc);
+    const int step = nq * 32;
+    auto row_of = [&](int base, int& i, bool& valid, int& k0, int& k1) {
+        i = base + grp;
+        valid = i < r1;                                   // uniform inside the 8-lane group
+        const int ii = min(i, A.n - 1);
+        const int a0 = A.rp[ii], a1 = A.rp[ii + 1];
+        k0 = valid ? a0 : 0;
+        k1 = valid ? a1 : 0;
+    };
+    auto first = [&](int k0, int k1, int& c, T& a) {     // the lane's first entry (a = 0 past the row's end)
+        const int k = k0 + sub;
+        const int kc = max(0, min(k, k1 - 1));
+        c = A.ci[kc];
+        const T v = A.va[kc];
+        a = k < k1 ? v : zero<T>();
+    };
+    int base = r0 + q * 32;
+    if (base >= r1) return;
+    int i, k0, k1, c;
+    bool valid;
+    T a;
+    row_of(base, i, valid, k0, k1);
+    first(k0, k1, c, a);
+    for (; base < r1; base += step) {
+        int ni, nk0, nk1, nc;
+        bool nvalid;
+        T na;
+        row_of(base + step, ni, nvalid, nk0, nk1);
+        const W p0 = vfma(vup(a), vup(x[c]), vzero<W>());
+        W acc = k0 + sub < k1 ? p0 : vzero<W>();   // a lane past the row's end adds nothing
+        for (int k = k0 + sub + 8; k < k1; k += 8) acc = vfma(vup(A.va[k]), vup(x[A.ci[k]]), acc);
+        first(nk0, nk1, nc, na);
         acc = acc + shfl_xor_v(acc, 4);
         acc = acc + shfl_xor_v(acc, 2);
         acc = acc + shfl_xor_v(acc, 1);
         if (valid && sub == 0) y[i] = vdown<T>(acc);
+        i = ni;
+        valid = nvalid;
+        k0 = nk0;
+        k1 = nk1;
+        c = nc;
+        a = na;
     }
 }
 
