@@ -83,37 +83,47 @@ def test_first_iterations_full_convdiff3d(env, cfg2, method):
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
-def _golden_counts(grid=128):
-    """{method: {seed: iterations}} of converged oracle runs on the benchmark
-    workload (tests/golden/make_fullsize_counts.py)."""
+def _golden_runs(grid=128):
+    """{method: {seed: (status, iterations)}} of the oracle's runs on the
+    benchmark workload (tests/golden/make_fullsize_counts.py)."""
     out = {}
     for line in open(os.path.join(GOLDEN, "fullsize_iterations.txt")):
         f = line.split()
-        if f and not f[0].startswith("#") and int(f[0]) == grid and int(f[3]) == 0:
-            out.setdefault(f[1], {})[int(f[2])] = int(f[4])
+        if f and not f[0].startswith("#") and int(f[0]) == grid:
+            out.setdefault(f[1], {})[int(f[2])] = (int(f[3]), int(f[4]))
     return out
 
 
 @pytest.mark.parametrize("method", ["bl_bicg_rq", "egl_qmr", "bl_bicgstab_rq"])
 def test_fullsize_iteration_count(env, cfg2, method):
     """The benchmark's own solves, in its launch configuration (tol 1e-8, at
-    most 1200 iterations): the GPU's iteration count within 5% of the oracle's
-    count on the same inputs, plus the spread of the oracle's own counts over
-    runs with B perturbed by 1e-15 (where they are on file)."""
+    most 1200 iterations).  Where the oracle's run on the inputs themselves
+    converged: the GPU's iteration count within 5% of it, plus the spread of
+    the oracle's converged counts over runs with B perturbed by 1e-15.  Where
+    it did not (Bl-BiCG-rQ on this input runs to the cap with a growing
+    residual, while its 1e-15-perturbed copies converge): the GPU must
+    converge, with a count inside the range of the oracle's converged
+    perturbed runs widened by 5%."""
     P, ctx = env
     import torch
-    counts = _golden_counts().get(method, {})
-    if 0 not in counts:
+    runs = _golden_runs().get(method, {})
+    if 0 not in runs:
         pytest.skip(f"no oracle count on file for {method} (make_fullsize_counts.py --method {method})")
-    ref = counts[0]
-    spread = max(counts.values()) - min(counts.values())
+    conv = sorted(it for st, it in runs.values() if st == 0)
     A = P.Matrix.from_csr(ctx, cfg2.A)
     X, info = P.solve(ctx, A, torch.from_numpy(cfg2.B).cuda(), method, tol=1e-8, maxit=1200)
     A.close()
-    say(f"full 128^3 {method}: gpu it={info.iterations} status={info.status_name} | oracle it={ref} "
-        f"(perturbed-oracle counts {sorted(counts.values())}, spread {spread})")
+    st0, it0 = runs[0]
+    say(f"full 128^3 {method}: gpu it={info.iterations} status={info.status_name} | oracle on B: status={st0} "
+        f"it={it0} | converged oracle counts {conv}")
     assert info.status == 0
-    assert abs(info.iterations - ref) <= max(1, int(0.05 * ref)) + spread
+    if st0 == 0:
+        spread = max(conv) - min(conv)
+        assert abs(info.iterations - it0) <= max(1, int(0.05 * it0)) + spread
+    else:
+        assert len(conv) >= 2, "too few converged oracle runs on file"
+        lo, hi = min(conv), max(conv)
+        assert lo - max(1, int(0.05 * lo)) <= info.iterations <= hi + max(1, int(0.05 * hi))
 
 
 def _xstar_rows():
