@@ -134,6 +134,8 @@ typedef struct {
                                     * because the FP32 QR or inner solve failed
                                     * (breakdown, divergence) or an earlier FP32
                                     * step did not halve the true residual     */
+    int32_t single_workgroup;   /* 1 if the iterations ran in one single-workgroup
+                                 * launch (opts.fused_small), else 0           */
 } skr_result;
 
 /* Fill *opts with the defaults listed above. */

@@ -42,7 +42,8 @@ class skr_result(ctypes.Structure):
                 ("outer_iterations", ctypes.c_int32), ("breakdown_iter", ctypes.c_int32),
                 ("rel_res_recursive", ctypes.c_double), ("rel_res_true", ctypes.c_double),
                 ("history", ctypes.POINTER(ctypes.c_double)), ("history_cap", ctypes.c_int32),
-                ("history_len", ctypes.c_int32), ("fp64_outer_iterations", ctypes.c_int32)]
+                ("history_len", ctypes.c_int32), ("fp64_outer_iterations", ctypes.c_int32),
+                ("single_workgroup", ctypes.c_int32)]
 
 
 class skr_format_opts(ctypes.Structure):
@@ -297,6 +298,7 @@ class SolveInfo:
     rel_res_true: float
     history: np.ndarray = field(repr=False)
     fp64_outer_iterations: int = 0
+    single_workgroup: bool = False
 
     @property
     def status_name(self):
@@ -363,7 +365,8 @@ def solve(ctx: Context, A: Matrix, B, method: str, X=None, x0_zero: bool = False
                        int(adjoint), ctypes.byref(r))
     _check(ctx, rc)
     info = SolveInfo(r.status, r.iterations, r.matvecs, r.outer_iterations, r.breakdown_iter, r.rel_res_recursive,
-                     r.rel_res_true, hist[: r.history_len].copy(), r.fp64_outer_iterations)
+                     r.rel_res_true, hist[: r.history_len].copy(), r.fp64_outer_iterations,
+                     bool(r.single_workgroup))
     return X, info
 
 

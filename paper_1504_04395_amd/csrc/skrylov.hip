@@ -729,10 +729,11 @@ int solve_fp64(skr_context* c, const skr_matrix* M, int s, const T* B, T* X, boo
         return SKR_BREAKDOWN;
     }
     e.pc_on = e.pc != nullptr;
-    InnerStats st = small_eligible<T>(c, e, method, o)
-                        ? iterate_small<T>(c, e, method, o.tol, o.maxit, rhs, D)
-                        : iterate<T>(c, e, m, method, o.tol, o.maxit, o.check_every, o.use_graph != 0,
-                                     fnv(&e.pc, sizeof(e.pc), fnv(&ar, sizeof(ar), 0)));
+    const bool small = small_eligible<T>(c, e, method, o);
+    InnerStats st = small ? iterate_small<T>(c, e, method, o.tol, o.maxit, rhs, D)
+                          : iterate<T>(c, e, m, method, o.tol, o.maxit, o.check_every, o.use_graph != 0,
+                                       fnv(&e.pc, sizeof(e.pc), fnv(&ar, sizeof(ar), 0)));
+    res->single_workgroup = small ? 1 : 0;
     e.pc_on = false;
     if (e.pc) {   // the method solved A M^-1 D = Q: the correction is M^-1 D
         prec_apply(e, s, D, e.pc_tmp, false, nullptr);

@@ -72,6 +72,7 @@ def test_fixed_iterations_match_oracle(pkg, ctx, kind, n, s, method):
     A = pkg.Matrix.from_csr(ctx, C)
     X, info = pkg.solve(ctx, A, B, method, tol=0.0, maxit=8)
     A.close()
+    assert info.single_workgroup   # the single-workgroup kernel ran
     assert info.iterations == 8 and info.status == ref.status   # not converged, or diverged (||R_8|| > ||R_0||)
     assert info.matvecs == ref.matvecs
     assert _rel(X, ref.X) < 1e-10, _rel(X, ref.X)
@@ -94,6 +95,7 @@ def test_converged_matches_general_schedule(pkg, ctx, kind, n, s, method):
     A.close()
     say(f"  fused it={i1.iterations} general it={i2.iterations} oracle it={ref.iterations} "
         f"res={i1.rel_res_true:.2e}")
+    assert i1.single_workgroup and not i2.single_workgroup
     assert i1.status == i2.status == ref.status == 0
     assert abs(i1.iterations - i2.iterations) <= 1 + int(0.02 * i2.iterations)
     assert abs(i1.iterations - ref.iterations) <= 1 + int(0.05 * ref.iterations)
@@ -133,6 +135,7 @@ def test_one_row_and_size_limits(pkg, ctx, method):
         A = pkg.Matrix.from_csr(ctx, C)
         X, info = pkg.solve(ctx, A, B, method, tol=0.0, maxit=6)
         A.close()
+        assert info.single_workgroup == (n <= 1024)
         assert info.iterations == 6 and _rel(X, ref.X) < 1e-10
 
 
