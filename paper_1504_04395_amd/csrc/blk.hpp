@@ -281,7 +281,7 @@ __device__ inline void tile_load(const T* P, int b, int r1, int s, int c, int q,
     for (int v = 0; v < 4; ++v) {
         const int i = b + 4 * v + q;
         const bool ok = i < r1 && c < s;
-        const double val = (double)P[(size_t)(ok ? i : b) * s + (ok ? c : 0)];
+        const double val = (double)ld_nt(&P[(size_t)(ok ? i : b) * s + (ok ? c : 0)]);
         x[v] = ok ? val : 0.0;
     }
 }
