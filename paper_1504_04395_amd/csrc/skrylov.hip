@@ -165,6 +165,8 @@ struct skr_context {
     Ctl* hout = nullptr;  // pinned
     c64* hsum = nullptr;  // pinned, small
     c64* hmat = nullptr;  // pinned, kMaxS x kMaxS: s x s results of the allocation-free calls
+    double* hhist = nullptr;   // pinned residual history of the single-workgroup path (grow-only)
+    size_t hhist_cap = 0;      // entries
     char* scratch = nullptr;   // device address of this device's static scratch array (or null)
     int lds_max = 0;           // LDS bytes one workgroup may hold on this device
     std::vector<GraphEntry> graphs;
@@ -489,9 +491,10 @@ struct InnerStats {
     std::vector<double> hist;
 };
 
-// Stop state (already copied to c->hout) and history of a finished run.
+// Stop state (already copied to c->hout) and history of a finished run (read
+// from the device, or from host_hist where the caller has already copied it).
 template <class T>
-InnerStats inner_stats(skr_context* c, Env<T>& e, long long mv_per_iter) {
+InnerStats inner_stats(skr_context* c, Env<T>& e, long long mv_per_iter, const double* host_hist = nullptr) {
     InnerStats r;
     const Ctl& o = *c->hout;
     r.iters = o.iter;
@@ -500,7 +503,10 @@ InnerStats inner_stats(skr_context* c, Env<T>& e, long long mv_per_iter) {
     r.matvecs = (long long)o.iter * mv_per_iter;
     r.rres = o.nr0 > 0 ? o.res / o.nr0 : 0.0;
     r.hist.resize((size_t)o.iter + 1);
-    SKR_HIP(hipMemcpy(r.hist.data(), e.hist, sizeof(double) * r.hist.size(), hipMemcpyDeviceToHost));
+    if (host_hist)
+        std::memcpy(r.hist.data(), host_hist, sizeof(double) * r.hist.size());
+    else
+        SKR_HIP(hipMemcpy(r.hist.data(), e.hist, sizeof(double) * r.hist.size(), hipMemcpyDeviceToHost));
     return r;
 }
 
@@ -607,11 +613,12 @@ void launch_small(Env<T>& e, int method, size_t lds, const T* rhs, T* D) {
     }
 }
 
-// Run Gl-BiCG, eGl-BiCG or Gl-BiCGStab on A D = rhs in one launch (every
-// iteration inside one workgroup); same stopping rule, breakdown rules and
-// history as iterate.
+// Enqueue Gl-BiCG, eGl-BiCG or Gl-BiCGStab on A D = rhs as one launch (every
+// iteration inside one workgroup; same stopping rule, breakdown rules and
+// history as iterate), then the copy of the stop state to c->hout.  The caller
+// synchronises and reads the result with inner_stats.
 template <class T>
-InnerStats iterate_small(skr_context* c, Env<T>& e, int method, double tol, int maxit, const T* rhs, T* D) {
+void enqueue_small(skr_context* c, Env<T>& e, int method, double tol, int maxit, const T* rhs, T* D) {
     Ctl* h = c->hin;
     std::memset(h, 0, sizeof(Ctl));
     h->status = ST_RUNNING;
@@ -637,21 +644,41 @@ InnerStats iterate_small(skr_context* c, Env<T>& e, int method, double tol, int 
     }
     SKR_LAUNCHED();
     SKR_HIP(hipMemcpyAsync(c->hout, e.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, e.st));
-    SKR_HIP(hipStreamSynchronize(e.st));
-    return inner_stats(c, e, method == SKR_EGL_BICG ? (long long)e.s + 1 : 2LL * e.s);
 }
 
-// True residual: part = (||B - A X||^2, ||B||^2) -> host
+// True residual: part = (||B - A X||^2, ||B||^2) -> c->hsum[0..1].x; with
+// sync = false only enqueued (the caller synchronises before reading).
 template <class T>
-void true_residual(skr_context* c, Env<T>& e, const T* B, const T* X, T* tmp, double* rn2, double* bn2) {
+void true_residual(skr_context* c, Env<T>& e, const T* B, const T* X, T* tmp, double* rn2, double* bn2,
+                   bool sync = true) {
     spmm(e, e.A, e.ly, X, tmp, EpiNone{}, (const Ctl*)nullptr);
     k_resid<T, T><<<e.nb, kBlock, 0, e.st>>>(e.fl, B, tmp, (T*)nullptr, (T*)nullptr, e.part);
     k_sum2<<<1, kScalar, 0, e.st>>>(e.part, e.nb, e.sc + 100);
     SKR_LAUNCHED();
     SKR_HIP(hipMemcpyAsync(c->hsum, e.sc + 100, 2 * sizeof(c64), hipMemcpyDeviceToHost, e.st));
+    if (!sync) return;
     SKR_HIP(hipStreamSynchronize(e.st));
     *rn2 = c->hsum[0].x;
     *bn2 = c->hsum[1].x;
+}
+
+// Pinned host room for n history entries (grow-only; null when n is beyond
+// the cap below, and then the history is read with a blocking copy).
+inline double* host_history(skr_context* c, size_t n) {
+    constexpr size_t kCap = size_t(1) << 16;   // 512 KB
+    if (n > kCap) return nullptr;
+    if (n > c->hhist_cap) {
+        if (c->hhist) {
+            SKR_HIP(hipStreamSynchronize(c->stream()));
+            (void)hipHostFree(c->hhist);
+            c->hhist = nullptr;
+            c->hhist_cap = 0;
+        }
+        const size_t want = std::max<size_t>(n, 4096);
+        SKR_HIP(hipHostMalloc((void**)&c->hhist, sizeof(double) * want, hipHostMallocDefault));
+        c->hhist_cap = want;
+    }
+    return c->hhist;
 }
 
 // Preprocess rhs in place: rhs = Q with rhs = Q R_R (R_R -> mats M_RB).  Returns
@@ -730,20 +757,36 @@ int solve_fp64(skr_context* c, const skr_matrix* M, int s, const T* B, T* X, boo
     }
     e.pc_on = e.pc != nullptr;
     const bool small = small_eligible<T>(c, e, method, o);
-    InnerStats st = small ? iterate_small<T>(c, e, method, o.tol, o.maxit, rhs, D)
-                          : iterate<T>(c, e, m, method, o.tol, o.maxit, o.check_every, o.use_graph != 0,
-                                       fnv(&e.pc, sizeof(e.pc), fnv(&ar, sizeof(ar), 0)));
+    InnerStats st;
+    double rn2, bn2;
+    if (small) {
+        // one launch, then X = X0 + D R_R, the true residual and the history
+        // copy, all enqueued behind it, and one synchronisation for the lot
+        enqueue_small<T>(c, e, method, o.tol, o.maxit, rhs, D);
+        k_xupd<T, T, J><<<e.nb, kBlock, mat_lds(s, 1, 1), e.st>>>(e.tl, e.mats, pre ? M_RB : -1, X, D, 0);
+        SKR_LAUNCHED();
+        true_residual<T>(c, e, B, X, tmp, &rn2, &bn2, false);
+        double* hh = host_history(c, (size_t)o.maxit + 1);
+        if (hh) SKR_HIP(hipMemcpyAsync(hh, e.hist, sizeof(double) * ((size_t)o.maxit + 1), hipMemcpyDeviceToHost, e.st));
+        SKR_HIP(hipStreamSynchronize(e.st));
+        rn2 = c->hsum[0].x;
+        bn2 = c->hsum[1].x;
+        st = inner_stats(c, e, method == SKR_EGL_BICG ? (long long)e.s + 1 : 2LL * e.s, hh);
+    } else {
+        st = iterate<T>(c, e, m, method, o.tol, o.maxit, o.check_every, o.use_graph != 0,
+                        fnv(&e.pc, sizeof(e.pc), fnv(&ar, sizeof(ar), 0)));
+        e.pc_on = false;
+        if (e.pc) {   // the method solved A M^-1 D = Q: the correction is M^-1 D
+            prec_apply(e, s, D, e.pc_tmp, false, nullptr);
+            D = e.pc_tmp;
+        }
+        // X = X0 + D R_R  (or X0 + D)
+        k_xupd<T, T, J><<<e.nb, kBlock, mat_lds(s, 1, 1), e.st>>>(e.tl, e.mats, pre ? M_RB : -1, X, D, 0);
+        SKR_LAUNCHED();
+        true_residual<T>(c, e, B, X, tmp, &rn2, &bn2);
+    }
     res->single_workgroup = small ? 1 : 0;
     e.pc_on = false;
-    if (e.pc) {   // the method solved A M^-1 D = Q: the correction is M^-1 D
-        prec_apply(e, s, D, e.pc_tmp, false, nullptr);
-        D = e.pc_tmp;
-    }
-    // X = X0 + D R_R  (or X0 + D)
-    k_xupd<T, T, J><<<e.nb, kBlock, mat_lds(s, 1, 1), e.st>>>(e.tl, e.mats, pre ? M_RB : -1, X, D, 0);
-    SKR_LAUNCHED();
-    double rn2, bn2;
-    true_residual<T>(c, e, B, X, tmp, &rn2, &bn2);
     double rel = bn2 > 0 ? std::sqrt(rn2 / bn2) : 0.0;
     res->status = st.status;
     if (st.status != SKR_BREAKDOWN && rel > 1.0) res->status = SKR_DIVERGED;
@@ -1020,6 +1063,7 @@ int skr_context_destroy(skr_context* c) {
     if (c->hout) (void)hipHostFree(c->hout);
     if (c->hsum) (void)hipHostFree(c->hsum);
     if (c->hmat) (void)hipHostFree(c->hmat);
+    if (c->hhist) (void)hipHostFree(c->hhist);
     if (c->own) (void)hipStreamDestroy(c->own);
     delete c;
     return SKR_OK;
