@@ -185,3 +185,23 @@ def test_repeatable_bit_for_bit(pkg, ctx):
         assert i1.iterations == i2.iterations and np.array_equal(X1, X2)
         np.testing.assert_array_equal(i1.history, i2.history)
     A.close()
+
+
+def test_history_copy_paths(pkg, ctx):
+    """The residual history reaches the caller whole on both of its routes (a
+    pinned copy enqueued behind the kernel for maxit + 1 <= 65536 entries, a
+    blocking copy above that) and is cut to the caller's history_cap."""
+    C = I.convdiff2d(32)
+    B = I.gaussian_block(C.n, 4, seed=6)
+    A = pkg.Matrix.from_csr(ctx, C)
+    for method in FUSED:
+        X1, i1 = pkg.solve(ctx, A, B, method, tol=1e-10, maxit=10000)
+        X2, i2 = pkg.solve(ctx, A, B, method, tol=1e-10, maxit=100000)
+        X3, i3 = pkg.solve(ctx, A, B, method, tol=1e-10, maxit=10000, history_cap=5)
+        assert i1.single_workgroup and i2.single_workgroup and i3.single_workgroup
+        assert i1.status_name == i2.status_name == "ok" and i1.iterations == i2.iterations == i3.iterations
+        assert len(i1.history) == len(i2.history) == i1.iterations + 1
+        np.testing.assert_array_equal(i1.history, i2.history)
+        np.testing.assert_array_equal(i3.history, i1.history[:5])
+        assert np.array_equal(X1, X2) and np.array_equal(X1, X3)
+    A.close()
