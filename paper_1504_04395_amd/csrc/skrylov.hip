@@ -681,19 +681,45 @@ inline double* host_history(skr_context* c, size_t n) {
     return c->hhist;
 }
 
+template <class T, int S>
+void launch_small_qr(Env<T>& e, T* rhs) {
+    k_small_qr<T, S><<<1, kSmallThreads, 0, e.st>>>(e.ctl, e.n, rhs, e.mats, 0x1p-53);
+}
+
 // Preprocess rhs in place: rhs = Q with rhs = Q R_R (R_R -> mats M_RB).  Returns
-// false if the QR broke down.
+// false if the QR broke down.  small: the system takes the single-workgroup
+// path (n <= 1024, s within its limit), and the QR runs as one launch too.
 template <class T, int J>
-bool preprocess(skr_context* c, Env<T>& e, T* rhs) {
+bool preprocess(skr_context* c, Env<T>& e, T* rhs, bool small = false) {
     Ctl* h = c->hin;
     std::memset(h, 0, sizeof(Ctl));
     h->status = ST_RUNNING;
     h->bd_iter = -1;
     SKR_HIP(hipMemcpyAsync(e.ctl, h, sizeof(Ctl), hipMemcpyHostToDevice, e.st));
-    k_bl_gram<T, J><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.tl, rhs, rhs, e.part);
-    SKR_LAUNCHED();
-    cholqr<T, J>(e, 0, rhs, rhs, 0, nullptr);
-    k_copy_mat<<<1, kScalar, 0, e.st>>>(e.mats, e.s, M_S, M_RB);
+    if (small) {
+        if constexpr (!std::is_same<typename Tr<T>::R, double>::value) {
+            throw Unsupported{"single-workgroup path: FP64 only"};
+        } else if constexpr (Tr<T>::cplx) {
+            switch (e.s) {
+                case 1: launch_small_qr<T, 1>(e, rhs); break;
+                case 2: launch_small_qr<T, 2>(e, rhs); break;
+                default: throw Unsupported{"single-workgroup path: block too wide"};
+            }
+        } else {
+            switch (e.s) {
+                case 1: launch_small_qr<T, 1>(e, rhs); break;
+                case 2: launch_small_qr<T, 2>(e, rhs); break;
+                case 3: launch_small_qr<T, 3>(e, rhs); break;
+                case 4: launch_small_qr<T, 4>(e, rhs); break;
+                default: throw Unsupported{"single-workgroup path: block too wide"};
+            }
+        }
+    } else {
+        k_bl_gram<T, J><<<e.nb, kBlock, 0, e.st>>>(e.ctl, e.tl, rhs, rhs, e.part);
+        SKR_LAUNCHED();
+        cholqr<T, J>(e, 0, rhs, rhs, 0, nullptr);
+        k_copy_mat<<<1, kScalar, 0, e.st>>>(e.mats, e.s, M_S, M_RB);
+    }
     SKR_LAUNCHED();
     SKR_HIP(hipMemcpyAsync(c->hout, e.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, e.st));
     SKR_HIP(hipStreamSynchronize(e.st));
@@ -749,14 +775,14 @@ int solve_fp64(skr_context* c, const skr_matrix* M, int s, const T* B, T* X, boo
     }
     SKR_LAUNCHED();
     bool pre = o.preprocess_qr != 0;
-    if (pre && !preprocess<T, J>(c, e, rhs)) {
+    const bool small = small_eligible<T>(c, e, method, o);
+    if (pre && !preprocess<T, J>(c, e, rhs, small)) {
         res->status = SKR_BREAKDOWN;
         res->iterations = 0;
         res->breakdown_iter = 0;
         return SKR_BREAKDOWN;
     }
     e.pc_on = e.pc != nullptr;
-    const bool small = small_eligible<T>(c, e, method, o);
     InnerStats st;
     double rn2, bn2;
     if (small) {

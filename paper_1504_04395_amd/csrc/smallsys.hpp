@@ -16,8 +16,10 @@
 // dominate small systems on the general schedule.
 #pragma once
 
+#include "blk.hpp"
 #include "common.hpp"
 #include "glk.hpp"
+#include "small.hpp"
 #include "spmm.hpp"
 
 namespace skr {
@@ -437,6 +439,113 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_bicgstab(Ctl* ctl, doub
 #pragma unroll
         for (int c = 0; c < S; ++c) x[(size_t)i * s + c] = X[c];
     }
+}
+
+// acc + z m for one entry of a row times an s x s matrix (the matrix is held as
+// complex FP64; its imaginary parts are zero for real data)
+__device__ inline double smac(double z, c64 m, double acc) { return fma(z, m.x, acc); }
+__device__ inline c64 smac(c64 z, c64 m, c64 acc) {
+    return {fma(z.x, m.x, fma(-z.y, m.y, acc.x)), fma(z.x, m.y, fma(z.y, m.x, acc.y))};
+}
+
+// The QR preprocessing of the block of initial residuals (Section 5) for the
+// single-workgroup path, in one launch: thread i keeps row i of Z.  The same
+// shifted CholeskyQR2 as the general schedule's k_qr_chol passes (the same
+// factorisations, shift and breakdown tests, through the same device
+// functions), on Grams summed in the fixed order of the small kernels: pass 1
+// factors Z^H Z (shifted if the plain factorisation fails), pass 2 the Gram of
+// Q1 = Z S1^{-1}, pass 3 (shifted case only) that of Q2 = Q1 S2^{-1}.  Z is
+// overwritten by Q and the R factor S_k ... S_1 is written to M_S and M_RB; a
+// failed factorisation records a breakdown in ctl and leaves Z unchanged.
+template <class T, int S>
+__global__ __launch_bounds__(kSmallThreads) void k_small_qr(Ctl* ctl, int n, T* __restrict__ Z, c64* __restrict__ mats,
+                                                            double u) {
+    constexpr int s = S, ss = S * S, NW = kSmallThreads / 64;
+    using V = Val<T>;
+    __shared__ V red[NW][ss];
+    __shared__ c64 G[ss], Am[ss], Bm[ss], Rm[ss], Dm[ss];
+    __shared__ int flag;
+    const int i = threadIdx.x, lane = i & 63, w = i >> 6;
+    T q[S];
+#pragma unroll
+    for (int b = 0; b < S; ++b) q[b] = T{};
+    if (i < n) {
+#pragma unroll
+        for (int b = 0; b < S; ++b) q[b] = Z[(size_t)i * s + b];
+    }
+    // G = q^H q over all rows: each wave's sums, then the 16 wave sums in order
+    auto gram = [&]() {
+#pragma unroll
+        for (int a = 0; a < S; ++a) {
+#pragma unroll
+            for (int b = 0; b < S; ++b) {
+                const V g = swave(sdot(q[a], q[b], V{}));
+                if (lane == 0) red[w][a * S + b] = g;
+            }
+        }
+        __syncthreads();
+        if (i < ss) {
+            V t = red[0][i];
+            for (int k = 1; k < NW; ++k) t = t + red[k][i];
+            G[i] = sc64(t);
+        }
+        __syncthreads();
+    };
+    // q = q M (M upper triangular, in LDS)
+    auto apply = [&](const c64* M) {
+        T r[S];
+#pragma unroll
+        for (int b = 0; b < S; ++b) {
+            T acc{};
+#pragma unroll
+            for (int a = 0; a < S; ++a) acc = smac(q[a], M[a * S + b], acc);
+            r[b] = acc;
+        }
+#pragma unroll
+        for (int b = 0; b < S; ++b) q[b] = r[b];
+    };
+    gram();
+    sm_copy(Am, G, ss);
+    int ok = sm_cholesky(Am, s, 0.0, &flag, 1e4 * u);
+    int shifted = 0;
+    if (!ok) {
+        double trg = 0.0;
+        for (int k = 0; k < s; ++k) trg += G[k * s + k].x;
+        const double shift = fmax(11.0 * ((double)n * s + (double)s * (s + 1)) * 0x1p-53, 1e3 * u) * trg;
+        sm_copy(Am, G, ss);
+        ok = sm_cholesky(Am, s, shift, &flag, fmax(1e2 * u, 1e-12));
+        shifted = 1;
+    }
+    if (!ok) {   // uniform: every thread holds the same flag
+        if (i == 0) set_breakdown(ctl);
+        return;
+    }
+    sm_tri_inv_upper(Am, Bm, s);   // S1^{-1}
+    sm_copy(Rm, Am, ss);
+    apply(Bm);
+    const int passes = shifted ? 3 : 2;
+    for (int p = 2; p <= passes; ++p) {
+        gram();
+        sm_copy(Am, G, ss);
+        ok = sm_cholesky(Am, s, 0.0, &flag, fmax(1e2 * u, 1e-12));
+        if (!ok) {
+            if (i == 0) set_breakdown(ctl);
+            return;
+        }
+        sm_tri_inv_upper(Am, Bm, s);   // S_p^{-1}
+        sm_gemm(Dm, Am, 0, Rm, 0, s);  // S_p (S_{p-1} ... S_1)
+        sm_copy(Rm, Dm, ss);
+        apply(Bm);
+    }
+    if (i < n) {
+#pragma unroll
+        for (int b = 0; b < S; ++b) Z[(size_t)i * s + b] = q[b];
+    }
+    if (i < ss) {
+        mats[(size_t)M_S * ss + i] = Rm[i];
+        mats[(size_t)M_RB * ss + i] = Rm[i];
+    }
+    if (i == 0) ctl->qr_shift[0] = shifted;
 }
 
 }  // namespace skr

@@ -205,3 +205,31 @@ def test_history_copy_paths(pkg, ctx):
         np.testing.assert_array_equal(i3.history, i1.history[:5])
         assert np.array_equal(X1, X2) and np.array_equal(X1, X3)
     A.close()
+
+
+@pytest.mark.parametrize("method", FUSED)
+def test_ill_conditioned_rhs_shifted_qr(pkg, ctx, method):
+    """B with kappa about 1e9 (its third column the first plus 1e-9 noise): the
+    plain Cholesky factorisation of B^H B fails its pivot test, so the
+    preprocessing takes the shifted CholeskyQR2 (three passes).  The one-launch
+    QR of the single-workgroup path and the general schedule's multi-kernel
+    one then give the same converged X (1e-10), as does the oracle (its
+    Householder QR), with the true residual at the stopping level."""
+    C = I.convdiff2d(32)
+    B = I.gaussian_block(C.n, 3, seed=21)
+    noise = I.gaussian_block(C.n, 1, seed=22)[:, 0]
+    B[:, 2] = B[:, 0] + 1e-9 * noise
+    assert np.linalg.cond(B) > 1e8
+    say("fused shifted QR", method)
+    ref = O.solve(C, B, method, tol=1e-12, maxit=5000)
+    A = pkg.Matrix.from_csr(ctx, C)
+    X1, i1 = pkg.solve(ctx, A, B, method, tol=1e-12, maxit=5000)
+    X2, i2 = pkg.solve(ctx, A, B, method, tol=1e-12, maxit=5000, fused_small=False)
+    A.close()
+    say(f"  fused it={i1.iterations} general it={i2.iterations} oracle it={ref.iterations} "
+        f"res={i1.rel_res_true:.2e} {i2.rel_res_true:.2e}")
+    assert i1.single_workgroup and not i2.single_workgroup
+    assert i1.status_name == i2.status_name == "ok" and ref.status == 0
+    assert abs(i1.iterations - i2.iterations) <= 1 + int(0.02 * i2.iterations)
+    assert _rel(X1, X2) < 1e-10 and _rel(X1, ref.X) < 1e-10
+    assert i1.rel_res_true < 1e-11 and i2.rel_res_true < 1e-11
